@@ -1,0 +1,85 @@
+"""Seeded synthetic inputs: keys, IVs and IV lengths for the generator instances.
+
+This module holds no cipher arithmetic.  It serves both the HIP path and the oracle
+(tests and benchmark feed the same arrays to each).  Every draw comes from splitmix64
+(Steele, Lea and Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014):
+draw j of seed s is mix64(s + (j+1)*GAMMA) with GAMMA = 0x9E3779B97F4A7C15 and the
+published xor-shift-multiply finaliser, so any single draw is an O(1) pure function of
+(seed, j) and any instance can be regenerated alone for a sampled check.
+
+The paper draws its per-instance 80-bit IVs from an unspecified non-linear expansion of
+a pre-stored random set (Sec. IV-D) and does not say where keys come from; these recipes
+stand in for both.
+
+Recipes (instance i of n):
+  key  bytes = big-endian bytes of draw 4i (8 bytes) then the top 2 bytes of draw 4i+1
+  IV   bytes = big-endian bytes of draw 4i+2 then the top 2 bytes of draw 4i+3
+  IV length  (mixed-length workloads only) = {0, 32, 64, 80}[draw (4n + i) >> 62]
+"""
+from __future__ import annotations
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def mix64(z: np.ndarray) -> np.ndarray:
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def draws(seed: int, idx) -> np.ndarray:
+    """splitmix64 draw(s) number ``idx`` (0-based) of the stream seeded with ``seed``."""
+    j = np.asarray(idx, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        x = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + (j + np.uint64(1)) * GAMMA
+    return mix64(x)
+
+
+def _be_bytes(hi64: np.ndarray, lo64: np.ndarray) -> np.ndarray:
+    """[k] uint64 pairs -> [k, 10] bytes: 8 big-endian bytes of hi, top 2 bytes of lo."""
+    hi = np.asarray(hi64, dtype=np.uint64).astype(">u8").view(np.uint8).reshape(-1, 8)
+    lo = np.asarray(lo64, dtype=np.uint64).astype(">u8").view(np.uint8).reshape(-1, 8)[:, :2]
+    return np.ascontiguousarray(np.concatenate([hi, lo], axis=1))
+
+
+def keys_ivs(seed: int, n: int, idx=None):
+    """(keys, ivs) as uint8 [k, 10] for instances ``idx`` (default: all ``n``)."""
+    i = np.arange(n, dtype=np.uint64) if idx is None else np.asarray(idx, dtype=np.uint64)
+    f = np.uint64(4)
+    keys = _be_bytes(draws(seed, f * i), draws(seed, f * i + np.uint64(1)))
+    ivs = _be_bytes(draws(seed, f * i + np.uint64(2)), draws(seed, f * i + np.uint64(3)))
+    return keys, ivs
+
+
+def iv_lengths_mixed(seed: int, n: int, idx=None) -> np.ndarray:
+    """IV lengths uniform in {0, 32, 64, 80} bits (uint8 [k])."""
+    i = np.arange(n, dtype=np.uint64) if idx is None else np.asarray(idx, dtype=np.uint64)
+    sel = (draws(seed, np.uint64(4 * n) + i) >> np.uint64(62)).astype(np.int64)
+    return np.array([0, 32, 64, 80], dtype=np.uint8)[sel]
+
+
+def workload(name: str):
+    """Named workloads: (seed, n instances, keystream bits per instance, IV-length recipe)."""
+    table = {
+        # 1024 instances (32 slices x 32 lanes), 80-bit IVs, 4096 bits each
+        "plain-1k": (1, 1024, 4096, "80"),
+        # 2^22 instances, 80-bit IVs, 8192 bits each (4 GiB of bitsliced output)
+        "plain-4m": (2, 1 << 22, 8192, "80"),
+        # 2^20 instances, IV lengths in {0,32,64,80}, 65536 bits each, row-major u32+f32
+        "rowmajor-1m": (3, 1 << 20, 65536, "mixed"),
+    }
+    return table[name]
+
+
+def workload_inputs(name: str, idx=None):
+    """(keys, ivs, iv_bits or None) for a named workload (optionally a subset ``idx``)."""
+    seed, n, _, ivr = workload(name)
+    keys, ivs = keys_ivs(seed, n, idx)
+    ivb = None if ivr == "80" else iv_lengths_mixed(seed, n, idx)
+    return keys, ivs, ivb
