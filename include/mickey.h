@@ -1,0 +1,148 @@
+/*
+ * mickey.h - C ABI of libmickey.so: bitsliced MICKEY 2.0 keystream generation on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper Sec. II-C-1 and Sec. IV-D): n independent MICKEY 2.0 generator
+ * instances, each with its own 80-bit key and an IV of 0..80 bits, are packed one per
+ * bit lane of 32-bit words; the two 100-bit registers R and S become 200 words per
+ * group of 32 instances, and every clock advances all lanes at once.  Bitslicing only
+ * changes the layout: instance i produces exactly the keystream of the MICKEY 2.0
+ * definition (the cipher specification the paper cites), bit for bit.
+ *
+ * Conventions
+ *   - Bits of keys and IVs are read MSB first: key bit j is bit (7 - j%8) of byte j/8.
+ *   - z_t is keystream bit t of an instance (t = 0 is the first bit after the 100
+ *     preclocks of the initialisation).
+ *   - n is padded internally to n_pad = 64*ceil(n/64) instances; pad instances run with
+ *     an all-zero key and an all-zero 80-bit IV.
+ *
+ * Output layouts (mickey_generate):
+ *   MICKEY_BITSLICED    plane-major bit-planes.  Plane t (t = 0..nbits-1) holds z_t of
+ *                       every instance as an LSB-first bit vector of n_pad bits:
+ *                       instance i is bit (i % 8) of byte (t*pitch + i/8), where
+ *                       pitch = mickey_plane_pitch(n) = n_pad/8 bytes.  The buffer is
+ *                       nbits*pitch bytes.  Bits of pad instances hold their (zero
+ *                       key) keystream and are not part of the result.
+ *   MICKEY_ROWMAJOR_U32 instance-major 32-bit words: word j of instance i is
+ *                       out[i*(nbits/32) + j], and bit (31 - b) of it is z_{32j+b}.
+ *                       Needs nbits % 32 == 0.  Buffer: n*nbits/8 bytes.
+ *   MICKEY_ROWMAJOR_F32 the same words w as floats (w >> 8) * 2^-24, exact, in
+ *                       [0, 1 - 2^-24].  Needs nbits % 32 == 0.  Buffer: n*nbits/8 bytes.
+ *
+ * Ownership and ordering
+ *   - The library owns a mickey_state and the device memory behind it.  The caller
+ *     owns every key, IV, length and output buffer; inputs may be reused as soon as the
+ *     call that reads them has completed on its stream.
+ *   - All device pointers are HIP device (or managed) pointers on the current device.
+ *   - Work is enqueued on the state's stream (the HIP null stream unless set) and is
+ *     asynchronous unless stated; results are valid after that stream synchronises.
+ *   - Calls on one state are not thread-safe.  Different states are independent.
+ *
+ * Errors: functions return MICKEY_OK (0) or a negative code; mickey_init returns NULL
+ * on error.  mickey_last_error() gives the calling thread's last code and
+ * mickey_last_error_message() a description.  A failed call leaves the state and its
+ * bit counter unchanged.
+ */
+#ifndef MICKEY_H
+#define MICKEY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MICKEY_OK 0
+#define MICKEY_EINVAL (-1)  /* bad argument: NULL pointer, n == 0, IV length > 80, layout */
+#define MICKEY_ENOMEM (-2)  /* device allocation failed */
+#define MICKEY_EDEVICE (-3) /* a HIP call or kernel launch failed */
+#define MICKEY_ERANGE (-4)  /* more than 2^40 keystream bits for one key/IV pair */
+#define MICKEY_ENOSYS (-5)  /* unsupported combination (e.g. word width) */
+
+#define MICKEY_BITSLICED 0
+#define MICKEY_ROWMAJOR_U32 1
+#define MICKEY_ROWMAJOR_F32 2
+
+/* Keystream bits allowed per key/IV pair (paper Sec. II-C-1: up to 2^40). */
+#define MICKEY_MAX_BITS_PER_IV ((uint64_t)1 << 40)
+
+typedef struct mickey_state mickey_state;
+
+/* Load n instances and run the initialisation of every one: registers cleared, then the
+ * IV bits, the 80 key bits and 100 zero bits clocked in with mixing on (the cipher's
+ * key/IV loading and preclock procedure; paper Sec. IV-D, bitsliced input handler).
+ *   keys    device, n*10 bytes, key of instance i at keys + 10*i
+ *   ivs     device, n*10 bytes, IV of instance i at ivs + 10*i (bits past its length
+ *           are ignored)
+ *   iv_bits device, n bytes, IV length of instance i in 0..80; NULL means 80 for all.
+ *           When non-NULL the lengths are validated, which synchronises the stream.
+ * Runs on the HIP null stream.  Returns NULL on error (see mickey_last_error). */
+mickey_state *mickey_init(const uint8_t *keys, const uint8_t *ivs, const uint8_t *iv_bits, size_t n);
+
+/* As mickey_init, on the given HIP stream (hipStream_t passed as void*), which becomes
+ * the state's stream. */
+mickey_state *mickey_init_on_stream(const uint8_t *keys, const uint8_t *ivs, const uint8_t *iv_bits,
+                                    size_t n, void *hip_stream);
+
+/* Re-run the initialisation of every instance of an existing state with new keys, IVs
+ * and IV lengths (same n, same arguments as mickey_init), reusing its device memory; the
+ * bit counter restarts at 0.  Asynchronous unless iv_bits is non-NULL. */
+int mickey_rekey(mickey_state *st, const uint8_t *keys, const uint8_t *ivs, const uint8_t *iv_bits);
+
+/* Advance every instance by nbits clocks and write the nbits keystream bits each one
+ * produced (bit z = r_0 xor s_0 of the state before each clock; paper Sec. IV-D: one
+ * word per 32 instances per clock) to `out` in `layout` (see above).  nbits >= 1; for
+ * the row-major layouts nbits % 32 == 0.  out: device, size as given by the layout.
+ * The next call continues with the following bit.  MICKEY_ERANGE if any instance would
+ * pass 2^40 bits in total. */
+int mickey_generate(mickey_state *st, uint64_t nbits, void *out, int layout);
+
+/* Row-major delivery of both forms in one pass: out_u32 and/or out_f32 (either may be
+ * NULL, not both), each n*nbits/8 bytes on the device, layouts as MICKEY_ROWMAJOR_U32
+ * and MICKEY_ROWMAJOR_F32.  nbits % 32 == 0. */
+int mickey_generate_rowmajor(mickey_state *st, uint64_t nbits, uint32_t *out_u32, float *out_f32);
+
+/* Release the state (synchronises its stream first).  NULL is allowed. */
+void mickey_free(mickey_state *st);
+
+/* Bind the state to a HIP stream (void* hipStream_t; NULL = null stream). */
+int mickey_set_stream(mickey_state *st, void *hip_stream);
+
+/* Slicing word width of the generate kernels: 32 (default; 32 instances per lane) or
+ * 64 (64 instances per lane, each state bit in a 64-bit word).  The output bytes do
+ * not depend on it. */
+int mickey_set_word_bits(mickey_state *st, int word_bits);
+
+size_t mickey_num_instances(const mickey_state *st);
+/* Keystream bits produced so far by each instance of the state. */
+uint64_t mickey_bits_generated(const mickey_state *st);
+/* Bytes per bit-plane of the MICKEY_BITSLICED layout for n instances: 8*ceil(n/64). */
+size_t mickey_plane_pitch(size_t n);
+
+/* Copy the 200 state bits of every instance into `packed` (device, n*25 bytes):
+ * instance i occupies bytes 25*i .. 25*i+24, and bit j of the string
+ * r_0..r_99 s_0..s_99 is bit (7 - j%8) of byte 25*i + j/8.  Also returns the bit
+ * counter in *bits_generated if that (host) pointer is non-NULL.  Asynchronous. */
+int mickey_state_export(const mickey_state *st, uint8_t *packed, uint64_t *bits_generated);
+
+/* Overwrite every instance's registers from `packed` (device, n*25 bytes, layout as in
+ * mickey_state_export) and set the bit counter; generation then resumes from there.
+ * Pad instances are left as they are.  Asynchronous. */
+int mickey_state_import(mickey_state *st, const uint8_t *packed, uint64_t bits_generated);
+
+/* Wait for all work enqueued on the state's stream. */
+int mickey_sync(mickey_state *st);
+
+int mickey_last_error(void);
+const char *mickey_last_error_message(void);
+
+/* Per-clock VALU instruction count of the generate clock for 32 instances (the
+ * algorithmic op count used for the VALU roofline).  Compile-time constant. */
+int mickey_ops_per_clock(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MICKEY_H */

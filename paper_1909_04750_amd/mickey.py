@@ -1,0 +1,214 @@
+"""ctypes binding of libmickey.so (include/mickey.h).  Argument marshalling only: every
+step of the keystream path runs in the library's HIP kernels; torch supplies device
+memory and the current stream.  There is no fallback: if the library is not built, or
+there is no GPU, calls raise."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from .build import LIB_PATH
+
+OK, EINVAL, ENOMEM, EDEVICE, ERANGE, ENOSYS = 0, -1, -2, -3, -4, -5
+BITSLICED, ROWMAJOR_U32, ROWMAJOR_F32 = 0, 1, 2
+MAX_BITS_PER_IV = 1 << 40
+PACKED_STATE_BYTES = 25
+
+EXPORTED = [
+    "mickey_init", "mickey_init_on_stream", "mickey_rekey", "mickey_generate", "mickey_generate_rowmajor",
+    "mickey_free", "mickey_set_stream", "mickey_set_word_bits", "mickey_num_instances",
+    "mickey_bits_generated", "mickey_plane_pitch", "mickey_state_export", "mickey_state_import",
+    "mickey_sync", "mickey_last_error", "mickey_last_error_message", "mickey_ops_per_clock",
+]
+
+_lib = None
+
+
+class MickeyError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (code %d)" % (msg, code))
+        self.code = code
+
+
+def load_library():
+    """Load lib/libmickey.so and declare its signatures (no GPU needed to load)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmickey.so is not built (run __graft_entry__.build()): " + LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, u64, i = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int
+    L.mickey_init.argtypes = [vp, vp, vp, sz]
+    L.mickey_init.restype = vp
+    L.mickey_init_on_stream.argtypes = [vp, vp, vp, sz, vp]
+    L.mickey_init_on_stream.restype = vp
+    L.mickey_rekey.argtypes = [vp, vp, vp, vp]
+    L.mickey_rekey.restype = i
+    L.mickey_generate.argtypes = [vp, u64, vp, i]
+    L.mickey_generate.restype = i
+    L.mickey_generate_rowmajor.argtypes = [vp, u64, vp, vp]
+    L.mickey_generate_rowmajor.restype = i
+    L.mickey_free.argtypes = [vp]
+    L.mickey_free.restype = None
+    L.mickey_set_stream.argtypes = [vp, vp]
+    L.mickey_set_stream.restype = i
+    L.mickey_set_word_bits.argtypes = [vp, i]
+    L.mickey_set_word_bits.restype = i
+    L.mickey_num_instances.argtypes = [vp]
+    L.mickey_num_instances.restype = sz
+    L.mickey_bits_generated.argtypes = [vp]
+    L.mickey_bits_generated.restype = u64
+    L.mickey_plane_pitch.argtypes = [sz]
+    L.mickey_plane_pitch.restype = sz
+    L.mickey_state_export.argtypes = [vp, vp, ctypes.POINTER(u64)]
+    L.mickey_state_export.restype = i
+    L.mickey_state_import.argtypes = [vp, vp, u64]
+    L.mickey_state_import.restype = i
+    L.mickey_sync.argtypes = [vp]
+    L.mickey_sync.restype = i
+    L.mickey_last_error.argtypes = []
+    L.mickey_last_error.restype = i
+    L.mickey_last_error_message.argtypes = []
+    L.mickey_last_error_message.restype = ctypes.c_char_p
+    L.mickey_ops_per_clock.argtypes = []
+    L.mickey_ops_per_clock.restype = i
+    _lib = L
+    return L
+
+
+def _check(rc: int) -> None:
+    if rc != OK:
+        L = load_library()
+        raise MickeyError(rc, L.mickey_last_error_message().decode())
+
+
+def plane_pitch(n: int) -> int:
+    return int(load_library().mickey_plane_pitch(n))
+
+
+def ops_per_clock() -> int:
+    return int(load_library().mickey_ops_per_clock())
+
+
+def _dev_ptr(t, name: str, nbytes: int):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError("%s holds %d bytes, needs %d" % (name, t.numel() * t.element_size(), nbytes))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Mickey:
+    """n bitsliced MICKEY 2.0 instances resident on the GPU (mickey_state)."""
+
+    def __init__(self, keys, ivs, iv_bits=None, stream=None):
+        n = int(keys.shape[0])
+        L = load_library()
+        kp = _dev_ptr(keys, "keys", 10 * n)
+        vp = _dev_ptr(ivs, "ivs", 10 * n)
+        bp = None if iv_bits is None else _dev_ptr(iv_bits, "iv_bits", n)
+        self._stream = stream
+        h = L.mickey_init_on_stream(kp, vp, bp, n, _stream_handle(stream))
+        if not h:
+            raise MickeyError(L.mickey_last_error(), L.mickey_last_error_message().decode())
+        self._h = ctypes.c_void_p(h)
+        self.n = n
+
+    def rekey(self, keys, ivs, iv_bits=None) -> None:
+        """Re-initialise all n instances with new keys/IVs (mickey_rekey)."""
+        kp = _dev_ptr(keys, "keys", 10 * self.n)
+        vp = _dev_ptr(ivs, "ivs", 10 * self.n)
+        bp = None if iv_bits is None else _dev_ptr(iv_bits, "iv_bits", self.n)
+        _check(load_library().mickey_rekey(self._h, kp, vp, bp))
+
+    # -- properties
+    @property
+    def bits_generated(self) -> int:
+        return int(load_library().mickey_bits_generated(self._h))
+
+    @property
+    def pitch(self) -> int:
+        return plane_pitch(self.n)
+
+    def set_word_bits(self, bits: int) -> None:
+        _check(load_library().mickey_set_word_bits(self._h, int(bits)))
+
+    def set_stream(self, stream) -> None:
+        _check(load_library().mickey_set_stream(self._h, _stream_handle(stream)))
+        self._stream = stream
+
+    # -- generation
+    def generate(self, nbits: int, layout: int = BITSLICED, out=None):
+        import torch
+        nbits = int(nbits)
+        if layout == BITSLICED:
+            nbytes = nbits * self.pitch
+            if out is None:
+                out = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        elif layout in (ROWMAJOR_U32, ROWMAJOR_F32):
+            nbytes = self.n * nbits // 8
+            if out is None:
+                dt = torch.int32 if layout == ROWMAJOR_U32 else torch.float32
+                out = torch.empty((self.n, nbits // 32), dtype=dt, device="cuda")
+        else:
+            raise ValueError("unknown layout %r" % layout)
+        p = _dev_ptr(out, "out", nbytes)
+        _check(load_library().mickey_generate(self._h, nbits, p, int(layout)))
+        return out
+
+    def generate_rowmajor(self, nbits: int, out_u32=None, out_f32=None, want_u32=True, want_f32=True):
+        import torch
+        nbits = int(nbits)
+        if want_u32 and out_u32 is None:
+            out_u32 = torch.empty((self.n, nbits // 32), dtype=torch.int32, device="cuda")
+        if want_f32 and out_f32 is None:
+            out_f32 = torch.empty((self.n, nbits // 32), dtype=torch.float32, device="cuda")
+        nbytes = self.n * nbits // 8
+        pu = None if out_u32 is None else _dev_ptr(out_u32, "out_u32", nbytes)
+        pf = None if out_f32 is None else _dev_ptr(out_f32, "out_f32", nbytes)
+        _check(load_library().mickey_generate_rowmajor(self._h, nbits, pu, pf))
+        return out_u32, out_f32
+
+    # -- state
+    def export_state(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.n, PACKED_STATE_BYTES), dtype=torch.uint8, device="cuda")
+        bits = ctypes.c_uint64(0)
+        _check(load_library().mickey_state_export(self._h, _dev_ptr(out, "packed", 25 * self.n),
+                                                  ctypes.byref(bits)))
+        return out, int(bits.value)
+
+    def import_state(self, packed, bits_generated: int) -> None:
+        _check(load_library().mickey_state_import(self._h, _dev_ptr(packed, "packed", 25 * self.n),
+                                                  int(bits_generated)))
+
+    def sync(self) -> None:
+        _check(load_library().mickey_sync(self._h))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load_library().mickey_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,53 @@
+"""CPU checks of the C-ABI library: it loads without a GPU and exports every function
+declared in include/mickey.h (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1909_04750_amd import build, mickey
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mickey.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(mickey_\w+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(build.LIB_PATH):
+        build.build_library()
+    return mickey.load_library()
+
+
+def test_header_declares_binding_symbols():
+    assert set(declared_functions()) == set(mickey.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    raw = ctypes.CDLL(build.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(raw, name), name
+
+
+def test_host_only_queries(lib):
+    assert mickey.plane_pitch(1) == 8
+    assert mickey.plane_pitch(64) == 8
+    assert mickey.plane_pitch(65) == 16
+    assert mickey.plane_pitch(1 << 22) == (1 << 22) // 8
+    assert mickey.ops_per_clock() == 328
+
+
+def test_null_state_is_rejected_without_gpu(lib):
+    assert lib.mickey_generate(None, 32, None, 0) == mickey.EINVAL
+    assert lib.mickey_last_error() == mickey.EINVAL
+    assert b"NULL" in lib.mickey_last_error_message()
+    assert lib.mickey_set_word_bits(None, 32) == mickey.EINVAL
+    assert lib.mickey_num_instances(None) == 0
+    lib.mickey_free(None)  # NULL-safe
