@@ -156,7 +156,7 @@ class Mickey:
             if out is None:
                 out = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         elif layout in (ROWMAJOR_U32, ROWMAJOR_F32):
-            nbytes = self.n * nbits // 8
+            nbytes = self.n * (nbits // 32) * 4  # the library rejects nbits % 32 != 0
             if out is None:
                 dt = torch.int32 if layout == ROWMAJOR_U32 else torch.float32
                 out = torch.empty((self.n, nbits // 32), dtype=dt, device="cuda")
@@ -173,7 +173,7 @@ class Mickey:
             out_u32 = torch.empty((self.n, nbits // 32), dtype=torch.int32, device="cuda")
         if want_f32 and out_f32 is None:
             out_f32 = torch.empty((self.n, nbits // 32), dtype=torch.float32, device="cuda")
-        nbytes = self.n * nbits // 8
+        nbytes = self.n * (nbits // 32) * 4
         pu = None if out_u32 is None else _dev_ptr(out_u32, "out_u32", nbytes)
         pf = None if out_f32 is None else _dev_ptr(out_f32, "out_f32", nbytes)
         _check(load_library().mickey_generate_rowmajor(self._h, nbits, pu, pf))
