@@ -24,7 +24,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "keystream Gbit/s on 1 MI355X (bit-exact vs oracle); served p50/p99 latency"
 WORKLOAD = "plain-4m"
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.32
+# 32-bit VALU lane-ops: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.64 T/s (the published fp32
+# vector peak, 157.3 TFLOP/s, counted as 2 flops per FMA lane-op)
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 

@@ -29,14 +29,58 @@ namespace {
 constexpr int kUnroll = 4;       // clocks per loop iteration of the generate kernels
 constexpr int kInitClocks = 260; // 80 IV slots + 80 key bits + 100 preclocks
 constexpr int kInputPlanes = 160;
-constexpr int kMaskPlanes = 80;
+constexpr int kMaskPlanes = 96;  // clocks 0..95 (lanes can only idle before clock 80)
 
 // ------------------------------------------------------------------------ kernels
 
-// a1: input staging.  One thread per instance; wave64 ballots turn each clock's input
-// bit of 64 instances into two 32-bit input words (the input handler of Sec. IV-D).
-// Instance i with IV length L idles for d = 80 - L clocks, then takes its L IV bits
-// (MSB first) so that the key always enters at clock 80 for every lane.
+// 32x32 bit transpose: on return a[r] bit c equals the input a[c] bit r.
+__device__ __forceinline__ void transpose32(uint32_t (&a)[32])
+{
+#pragma unroll
+    for (int i = 0; i < 32; i++) {
+        if (i & 16) continue;
+        const uint32_t x = a[i], y = a[i + 16];
+        a[i] = (x & 0x0000FFFFu) | (y << 16);
+        a[i + 16] = (x >> 16) | (y & 0xFFFF0000u);
+    }
+#pragma unroll
+    for (int i = 0; i < 32; i++) {
+        if (i & 8) continue;
+        const uint32_t x = a[i], y = a[i + 8];
+        a[i] = __builtin_amdgcn_bitop3_b32(x, y << 8, 0xFF00FF00u, (TA & ~TC) | (TB & TC));
+        a[i + 8] = __builtin_amdgcn_bitop3_b32(y, x >> 8, 0x00FF00FFu, (TA & ~TC) | (TB & TC));
+    }
+#pragma unroll
+    for (int i = 0; i < 32; i++) {
+        if (i & 4) continue;
+        const uint32_t x = a[i], y = a[i + 4];
+        a[i] = __builtin_amdgcn_bitop3_b32(x, y << 4, 0xF0F0F0F0u, (TA & ~TC) | (TB & TC));
+        a[i + 4] = __builtin_amdgcn_bitop3_b32(y, x >> 4, 0x0F0F0F0Fu, (TA & ~TC) | (TB & TC));
+    }
+#pragma unroll
+    for (int i = 0; i < 32; i++) {
+        if (i & 2) continue;
+        const uint32_t x = a[i], y = a[i + 2];
+        a[i] = __builtin_amdgcn_bitop3_b32(x, y << 2, 0xCCCCCCCCu, (TA & ~TC) | (TB & TC));
+        a[i + 2] = __builtin_amdgcn_bitop3_b32(y, x >> 2, 0x33333333u, (TA & ~TC) | (TB & TC));
+    }
+#pragma unroll
+    for (int i = 0; i < 32; i++) {
+        if (i & 1) continue;
+        const uint32_t x = a[i], y = a[i + 1];
+        a[i] = __builtin_amdgcn_bitop3_b32(x, y << 1, 0xAAAAAAAAu, (TA & ~TC) | (TB & TC));
+        a[i + 1] = __builtin_amdgcn_bitop3_b32(y, x >> 1, 0x55555555u, (TA & ~TC) | (TB & TC));
+    }
+}
+
+// a1: input staging (the bitsliced input handler of Sec. IV-D).  Instance i with IV
+// length L idles for d = 80 - L clocks and then takes its L IV bits (MSB first), so the
+// key always enters at clock 80 in every lane: its input string is the 160-bit number
+// (ivL << 80) | key read MSB first (ivL = the L-bit IV), and its "started" string is
+// d zeros then ones.  A block of 256 instances (8 slices) writes these strings as
+// 32-bit chunks to LDS; then one wave turns each (slice, chunk) into 32 bit-planes with
+// an in-register 32x32 bit transpose and stores them.
+template <bool MASKED>
 __global__ __launch_bounds__(256) void stage_kernel(const uint8_t *__restrict__ keys,
                                                     const uint8_t *__restrict__ ivs,
                                                     const uint8_t *__restrict__ iv_bits, uint32_t n,
@@ -44,11 +88,10 @@ __global__ __launch_bounds__(256) void stage_kernel(const uint8_t *__restrict__ 
                                                     uint32_t *__restrict__ mask_planes,
                                                     uint32_t *__restrict__ status)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    // n_pad = 32*nslices is a multiple of 64, so this retires whole waves only and the
-    // ballots below always see a full wave.
-    if (i >= nslices * 32u) return;
-    const uint32_t lane = threadIdx.x & 63u;
+    constexpr int kChunks = kInputPlanes / 32, kMaskChunks = kMaskPlanes / 32;
+    __shared__ uint32_t chunk[kChunks + kMaskChunks][256];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t i = blockIdx.x * 256u + tid;
     uint64_t kh = 0, ih = 0;
     uint32_t kl = 0, il = 0, L = 80;
     if (i < n) {
@@ -61,7 +104,7 @@ __global__ __launch_bounds__(256) void stage_kernel(const uint8_t *__restrict__ 
         }
         kl = ((uint32_t)k[8] << 8) | k[9];
         il = ((uint32_t)v[8] << 8) | v[9];
-        if (iv_bits) {
+        if (MASKED) {
             L = iv_bits[i];
             if (L > 80u) {
                 atomicOr(status, 1u);
@@ -69,28 +112,39 @@ __global__ __launch_bounds__(256) void stage_kernel(const uint8_t *__restrict__ 
             }
         }
     }
-    const uint32_t d = 80u - L;
-    const uint32_t word = (i >> 5);  // slice of this instance
-    for (uint32_t t = 0; t < (uint32_t)kInputPlanes; t++) {
-        uint32_t bit;
-        if (t < 80u) {
-            const uint32_t j = t - d;  // IV bit index when t >= d
-            const uint32_t vb = j < 64u ? (uint32_t)(ih >> (63u - j)) : (il >> (79u - j));
-            bit = (t >= d) ? (vb & 1u) : 0u;
-        } else {
-            const uint32_t j = t - 80u;
-            const uint32_t kb = j < 64u ? (uint32_t)(kh >> (63u - j)) : (kl >> (79u - j));
-            bit = kb & 1u;
-        }
-        const uint64_t bal = __ballot(bit);
-        if (lane == 0u) in_planes[(size_t)t * nslices + word] = (uint32_t)bal;
-        if (lane == 32u) in_planes[(size_t)t * nslices + word] = (uint32_t)(bal >> 32);
-        if (t < (uint32_t)kMaskPlanes) {
-            const uint64_t act = __ballot(t >= d);
-            if (lane == 0u) mask_planes[(size_t)t * nslices + word] = (uint32_t)act;
-            if (lane == 32u) mask_planes[(size_t)t * nslices + word] = (uint32_t)(act >> 32);
+    typedef unsigned __int128 u128;
+    const u128 key80 = ((u128)kh << 16) | kl;
+    const u128 iv80 = ((u128)ih << 16) | il;
+    const u128 ivL = L ? (iv80 >> (80u - L)) : (u128)0;
+    const u128 lo = key80 | (ivL << 80);  // bits 0..127 of the input string
+    chunk[0][tid] = (uint32_t)(ivL >> 48);  // bits 159..128: clocks 0..31, MSB first
+    chunk[1][tid] = (uint32_t)(lo >> 96);
+    chunk[2][tid] = (uint32_t)(lo >> 64);
+    chunk[3][tid] = (uint32_t)(lo >> 32);
+    chunk[4][tid] = (uint32_t)lo;
+    if (MASKED) {
+        const uint32_t d = 80u - L;  // clocks before this lane starts
+#pragma unroll
+        for (int c = 0; c < kMaskChunks; c++) {
+            const uint32_t first = 32u * c;  // "started" bit of clock first+b is (first+b >= d)
+            chunk[kChunks + c][tid] = d <= first ? 0xFFFFFFFFu : (d >= first + 32u ? 0u : (0xFFFFFFFFu >> (d - first)));
         }
     }
+    __syncthreads();
+    constexpr int kTasks = 8 * (kChunks + (MASKED ? kMaskChunks : 0));
+    static_assert(kTasks <= 64, "one wave does the transposes");
+    if (tid >= (uint32_t)kTasks) return;
+    const uint32_t sl = tid & 7u, c = tid >> 3;
+    const uint32_t slice = blockIdx.x * 8u + sl;
+    if (slice >= nslices) return;
+    uint32_t a[32];
+#pragma unroll
+    for (int l = 0; l < 32; l++) a[l] = chunk[c][32u * sl + l];
+    transpose32(a);  // a[r] bit l = chunk word of instance l, bit r = clock 32c' + 31 - r
+    uint32_t *dst = c < (uint32_t)kChunks ? in_planes + (size_t)(32u * c) * nslices
+                                          : mask_planes + (size_t)(32u * (c - kChunks)) * nslices;
+#pragma unroll
+    for (int r = 0; r < 32; r++) dst[(size_t)(31 - r) * nslices + slice] = a[r];
 }
 
 __device__ __forceinline__ uint32_t ld_plane(const uint32_t *base, size_t pitch, uint32_t t, uint32_t voff)
@@ -236,46 +290,6 @@ gen_bitsliced_kernel(uint32_t *__restrict__ state, uint32_t ngroups, uint32_t pi
         clock_gen<K>(x);
     }
     store_state<K>(x, state, pitch, voff);
-}
-
-// 32x32 bit transpose: on return a[r] bit c equals the input a[c] bit r.
-__device__ __forceinline__ void transpose32(uint32_t (&a)[32])
-{
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        if (i & 16) continue;
-        const uint32_t x = a[i], y = a[i + 16];
-        a[i] = (x & 0x0000FFFFu) | (y << 16);
-        a[i + 16] = (x >> 16) | (y & 0xFFFF0000u);
-    }
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        if (i & 8) continue;
-        const uint32_t x = a[i], y = a[i + 8];
-        a[i] = __builtin_amdgcn_bitop3_b32(x, y << 8, 0xFF00FF00u, (TA & ~TC) | (TB & TC));
-        a[i + 8] = __builtin_amdgcn_bitop3_b32(y, x >> 8, 0x00FF00FFu, (TA & ~TC) | (TB & TC));
-    }
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        if (i & 4) continue;
-        const uint32_t x = a[i], y = a[i + 4];
-        a[i] = __builtin_amdgcn_bitop3_b32(x, y << 4, 0xF0F0F0F0u, (TA & ~TC) | (TB & TC));
-        a[i + 4] = __builtin_amdgcn_bitop3_b32(y, x >> 4, 0x0F0F0F0Fu, (TA & ~TC) | (TB & TC));
-    }
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        if (i & 2) continue;
-        const uint32_t x = a[i], y = a[i + 2];
-        a[i] = __builtin_amdgcn_bitop3_b32(x, y << 2, 0xCCCCCCCCu, (TA & ~TC) | (TB & TC));
-        a[i + 2] = __builtin_amdgcn_bitop3_b32(y, x >> 2, 0x33333333u, (TA & ~TC) | (TB & TC));
-    }
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        if (i & 1) continue;
-        const uint32_t x = a[i], y = a[i + 1];
-        a[i] = __builtin_amdgcn_bitop3_b32(x, y << 1, 0xAAAAAAAAu, (TA & ~TC) | (TB & TC));
-        a[i + 1] = __builtin_amdgcn_bitop3_b32(y, x >> 1, 0x55555555u, (TA & ~TC) | (TB & TC));
-    }
 }
 
 // a3 + a5 + a6: keystream clocks with delivery as per-instance row-major words.  Each
@@ -425,8 +439,13 @@ int run_init(mickey_state *st, const uint8_t *keys, const uint8_t *ivs, const ui
     uint32_t *mask_planes = st->stage + (size_t)kInputPlanes * st->nslices;
     uint32_t *status = mask_planes + (size_t)kMaskPlanes * st->nslices;
     if (hipMemsetAsync(status, 0, 4, st->stream) != hipSuccess) return check_launch("hipMemsetAsync");
-    hipLaunchKernelGGL(stage_kernel, dim3((unsigned)((st->n_pad + 255) / 256)), dim3(256), 0, st->stream, keys,
-                       ivs, iv_bits, (uint32_t)st->n, (uint32_t)st->nslices, in_planes, mask_planes, status);
+    const dim3 sgrid((unsigned)((st->n_pad + 255) / 256));
+    if (iv_bits)
+        hipLaunchKernelGGL(stage_kernel<true>, sgrid, dim3(256), 0, st->stream, keys, ivs, iv_bits, (uint32_t)st->n,
+                           (uint32_t)st->nslices, in_planes, mask_planes, status);
+    else
+        hipLaunchKernelGGL(stage_kernel<false>, sgrid, dim3(256), 0, st->stream, keys, ivs, iv_bits,
+                           (uint32_t)st->n, (uint32_t)st->nslices, in_planes, mask_planes, status);
     int rc = check_launch("stage_kernel");
     if (rc != MICKEY_OK) return rc;
     const dim3 grid((unsigned)((st->nslices + 63) / 64));
@@ -451,10 +470,10 @@ int run_init(mickey_state *st, const uint8_t *keys, const uint8_t *ivs, const ui
 void destroy(mickey_state *st)
 {
     if (!st) return;
-    hipStreamSynchronize(st->stream);
-    if (st->planes) hipFree(st->planes);
-    if (st->stage) hipFree(st->stage);
-    if (st->host_status) hipHostFree(st->host_status);
+    (void)hipStreamSynchronize(st->stream);
+    if (st->planes) (void)hipFree(st->planes);
+    if (st->stage) (void)hipFree(st->stage);
+    if (st->host_status) (void)hipHostFree(st->host_status);
     delete st;
 }
 
@@ -484,7 +503,7 @@ mickey_state *init_impl(const uint8_t *keys, const uint8_t *ivs, const uint8_t *
     const size_t stage_bytes = (size_t)(kInputPlanes + kMaskPlanes) * pitch + 256;
     if (hipMalloc(&st->planes, 200 * pitch) != hipSuccess || hipMalloc(&st->stage, stage_bytes) != hipSuccess ||
         hipHostMalloc((void **)&st->host_status, 4, hipHostMallocDefault) != hipSuccess) {
-        hipGetLastError();
+        (void)hipGetLastError();
         destroy(st);
         fail(MICKEY_ENOMEM, "mickey_init: cannot allocate %zu bytes of device memory", 200 * pitch + stage_bytes);
         return nullptr;
