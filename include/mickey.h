@@ -134,6 +134,55 @@ int mickey_state_import(mickey_state *st, const uint8_t *packed, uint64_t bits_g
 /* Wait for all work enqueued on the state's stream. */
 int mickey_sync(mickey_state *st);
 
+/* ---------------------------------------------------------------------------------
+ * Batched generation (one persistent launch for many fresh requests).
+ *
+ * Each request is a fresh instance: its own key, IV of 0..80 bits and keystream length.
+ * The executor sorts the requests longest first into groups of 32 (one bit lane each
+ * of one slice), stages every group's input planes, and runs one persistent work-queue
+ * kernel whose waves pop groups of groups until the queue is empty.  The launch
+ * sequence is captured once as a HIP graph and replayed by mickey_batch_run.  The
+ * result of a request does not depend on the other requests of the batch.
+ */
+typedef struct mickey_batch mickey_batch;
+
+/* Executor for up to max_requests requests per batch, on a HIP stream (NULL: the
+ * executor creates and owns a stream; graph capture needs a non-null stream). */
+mickey_batch *mickey_batch_create(size_t max_requests, void *hip_stream);
+
+/* Set the requests that the following runs execute.
+ *   keys, ivs  device, 10 bytes per request (request r at offset 10*r)
+ *   iv_bits    device, one byte per request in 0..80, or NULL for 80 (validated here,
+ *              which synchronises the batch's stream)
+ *   nbits      host, keystream bits of request r: a multiple of 32, at most 2^37
+ *   outs       host array of device pointers: request r's nbits/32 words, laid out as
+ *              MICKEY_ROWMAJOR_U32 for one instance (bit 31-b of word j is z_{32j+b})
+ * Host arrays may be freed on return; device arrays must stay valid while runs use
+ * them.  Builds the sorted metadata and captures the launch graph. */
+int mickey_batch_set(mickey_batch *b, const uint8_t *keys, const uint8_t *ivs, const uint8_t *iv_bits,
+                     const uint64_t *nbits, uint32_t *const *outs, size_t nreq);
+
+/* Run the current requests: one graph launch (queue reset, input staging, the
+ * persistent kernel).  Asynchronous on the batch's stream. */
+int mickey_batch_run(mickey_batch *b);
+int mickey_batch_sync(mickey_batch *b);
+/* The batch's HIP stream (hipStream_t as void*). */
+void *mickey_batch_stream(const mickey_batch *b);
+
+/* Kernel variant: clocks per loop iteration (2, 4 or 8) and waves per workgroup (1, 2
+ * or 4); 0 keeps the current value.  Re-captures the graph. */
+int mickey_batch_set_params(mickey_batch *b, int unroll, int waves_per_block);
+int mickey_batch_get_params(const mickey_batch *b, int *unroll, int *waves_per_block);
+
+/* Autotuner: times every built variant on the current requests with lengths capped at
+ * cap_bits (a multiple of 32; outputs go to scratch memory), keeps the fastest and
+ * re-captures.  With cache_path, a JSON record of the choice is read from that file
+ * when its signature (architecture, request count, capped lengths) matches, and written
+ * there otherwise.  Synchronises the batch's stream. */
+int mickey_batch_autotune(mickey_batch *b, uint64_t cap_bits, const char *cache_path);
+
+void mickey_batch_free(mickey_batch *b);
+
 int mickey_last_error(void);
 const char *mickey_last_error_message(void);
 

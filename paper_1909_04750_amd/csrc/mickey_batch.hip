@@ -1,0 +1,479 @@
+// Batched generation: thousands of fresh MICKEY 2.0 requests of uneven keystream lengths
+// and IV lengths in one persistent, work-queue kernel launch, captured as a HIP graph.
+//
+// The requests are sorted longest first and packed 32 to a group (one slice: one bit
+// lane each); a task is 64 consecutive groups (one wave).  Waves pop tasks from a
+// device counter until the queue is empty, so the longest requests start first and
+// every wave exits once the counter passes the last task.  Each lane initialises its
+// group (with per-lane IV lengths, Sec. IV-D's input handler) and then runs as many
+// 32-clock row-major blocks as the longest request of the group needs; a request's
+// lane stops storing when its own words are done.
+#include "mickey_device.h"
+#include "mickey_host.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using namespace mickey;
+using namespace mickey_host;
+
+namespace {
+
+constexpr uint64_t kMaxBatchBits = (uint64_t)1 << 37;  // per request (32-bit word counts)
+
+__global__ void reset_words_kernel(uint32_t *p, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__global__ void check_iv_bits_kernel(const uint8_t *__restrict__ iv_bits, uint32_t n, uint32_t *status)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && iv_bits[i] > 80u) atomicOr(status, 1u);
+}
+
+// The persistent work-queue kernel.  Lane l of a wave working on task T owns group
+// g = 64T + l: slots 32g .. 32g+31, whose input planes are column g of the staged
+// planes (pitch gpitch words), and whose outputs are lane_out[32g + i] (lane_words
+// words each).  group_words[g] is the longest of them.
+template <int U, int WPB>
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void batch_kernel(
+    const uint32_t *__restrict__ in_planes, const uint32_t *__restrict__ mask_planes, uint32_t gpitch,
+    uint32_t ngroups, uint32_t ntasks, const uint32_t *__restrict__ group_words,
+    uint32_t *const *__restrict__ lane_out, const uint32_t *__restrict__ lane_words, uint32_t *__restrict__ counter)
+{
+    __shared__ uint32_t zbuf[32][64 * WPB];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u;
+    const size_t pitch = (size_t)gpitch * 4u;
+    for (;;) {
+        uint32_t task = 0;
+        if (lane == 0u) task = atomicAdd(counter, 1u);
+        task = __shfl(task, 0);
+        if (task >= ntasks) break;  // every wave leaves once the queue is drained
+        const uint32_t g = task * 64u + lane;  // < gpitch: planes exist for padding groups
+        const uint32_t nwords = g < ngroups ? group_words[g] : 0u;
+        Regs<1> x;
+        init_clocks<true, 4>(x, in_planes, mask_planes, pitch, g * 4u);
+        for (uint32_t j = 0; j < nwords; j++) {
+            rowmajor_block<U>(x, zbuf, tid, [&](int l, uint32_t w) {
+                const uint32_t slot = g * 32u + (uint32_t)l;
+                if (j < lane_words[slot]) lane_out[slot][j] = w;
+            });
+        }
+    }
+}
+
+typedef void (*BatchKernelFn)(const uint32_t *, const uint32_t *, uint32_t, uint32_t, uint32_t, const uint32_t *,
+                              uint32_t *const *, const uint32_t *, uint32_t *);
+
+struct Variant {
+    int unroll;
+    int wpb;
+    BatchKernelFn fn;
+};
+
+const Variant kVariants[] = {
+    {2, 1, batch_kernel<2, 1>}, {2, 2, batch_kernel<2, 2>}, {2, 4, batch_kernel<2, 4>},
+    {4, 1, batch_kernel<4, 1>}, {4, 2, batch_kernel<4, 2>}, {4, 4, batch_kernel<4, 4>},
+    {8, 1, batch_kernel<8, 1>}, {8, 2, batch_kernel<8, 2>}, {8, 4, batch_kernel<8, 4>},
+};
+
+const Variant *find_variant(int unroll, int wpb)
+{
+    for (const Variant &v : kVariants)
+        if (v.unroll == unroll && v.wpb == wpb) return &v;
+    return nullptr;
+}
+
+// Resident waves of the batch kernel on the whole GPU (2 per SIMD at 256 VGPRs).
+int resident_waves()
+{
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    return cus * 4 * 2;
+}
+
+}  // namespace
+
+struct mickey_batch {
+    size_t max_req = 0;
+    size_t max_groups_pad = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    // device buffers (one allocation)
+    void *dmem = nullptr;
+    uint32_t *order = nullptr;       // [slots] request of each slot, kNoRequest for padding
+    uint32_t **lane_out = nullptr;   // [slots]
+    uint32_t *lane_words = nullptr;  // [slots]
+    uint32_t *group_words = nullptr; // [groups]
+    uint32_t *counter = nullptr;     // work queue head
+    uint32_t *status = nullptr;      // IV length check
+    uint32_t *in_planes = nullptr;   // [160][groups_pad]
+    uint32_t *mask_planes = nullptr; // [96][groups_pad]
+    uint32_t *host_status = nullptr; // pinned
+    // current requests
+    const uint8_t *keys = nullptr, *ivs = nullptr, *iv_bits = nullptr;
+    size_t nreq = 0, ngroups = 0, groups_pad = 0, ntasks = 0;
+    std::vector<uint64_t> nbits;
+    std::vector<uint32_t *> outs;
+    std::vector<uint32_t> host_order;
+    int unroll = 4, wpb = 1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void drop_graph(mickey_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Enqueue the batch on b->stream: reset the queue head, stage the inputs of every slot,
+// launch the persistent kernel.
+int enqueue(mickey_batch *b, const Variant &v)
+{
+    hipLaunchKernelGGL(reset_words_kernel, dim3(1), dim3(64), 0, b->stream, b->counter, 2u);
+    int rc = check_launch("reset_words_kernel");
+    if (rc != MICKEY_OK) return rc;
+    const uint32_t nslots = (uint32_t)(b->groups_pad * 32);
+    const dim3 sgrid(nslots / 256 + (nslots % 256 ? 1 : 0));
+    if (b->iv_bits)
+        hipLaunchKernelGGL((stage_kernel<true, true>), sgrid, dim3(256), 0, b->stream, b->keys, b->ivs, b->iv_bits,
+                           b->order, nslots, (uint32_t)b->groups_pad, b->in_planes, b->mask_planes, b->status);
+    else
+        hipLaunchKernelGGL((stage_kernel<false, true>), sgrid, dim3(256), 0, b->stream, b->keys, b->ivs, b->iv_bits,
+                           b->order, nslots, (uint32_t)b->groups_pad, b->in_planes, b->mask_planes, b->status);
+    rc = check_launch("stage_kernel");
+    if (rc != MICKEY_OK) return rc;
+    const int waves = (int)std::min<size_t>(b->ntasks, (size_t)resident_waves());
+    const int blocks = (waves + v.wpb - 1) / v.wpb;
+    if (blocks > 0) {
+        hipLaunchKernelGGL(v.fn, dim3(blocks), dim3(64 * v.wpb), 0, b->stream, b->in_planes, b->mask_planes,
+                           (uint32_t)b->groups_pad, (uint32_t)b->ngroups, (uint32_t)b->ntasks, b->group_words,
+                           b->lane_out, b->lane_words, b->counter);
+        rc = check_launch("batch_kernel");
+    }
+    return rc;
+}
+
+int capture(mickey_batch *b)
+{
+    drop_graph(b);
+    const Variant *v = find_variant(b->unroll, b->wpb);
+    if (!v) return fail(MICKEY_EINVAL, "no batch kernel for unroll %d, %d waves per block", b->unroll, b->wpb);
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return check_launch("hipStreamBeginCapture");
+    int rc = enqueue(b, *v);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (rc != MICKEY_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(MICKEY_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    b->graph = g;
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(b);
+        return fail(MICKEY_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    return MICKEY_OK;
+}
+
+// Upload slot metadata for the given lengths and output pointers (sorted order kept).
+int upload_meta(mickey_batch *b, const std::vector<uint64_t> &nbits, const std::vector<uint32_t *> &outs)
+{
+    const size_t nslots = b->groups_pad * 32;
+    std::vector<uint32_t> words(nslots, 0u), gwords(b->groups_pad, 0u);
+    std::vector<uint32_t *> lo(nslots, nullptr);
+    for (size_t s = 0; s < nslots; s++) {
+        const uint32_t r = b->host_order[s];
+        if (r == kNoRequest) continue;
+        words[s] = (uint32_t)(nbits[r] / 32);
+        lo[s] = outs[r];
+        gwords[s / 32] = std::max(gwords[s / 32], words[s]);
+    }
+    if (hipMemcpyAsync(b->lane_words, words.data(), nslots * 4, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipMemcpyAsync(b->lane_out, lo.data(), nslots * sizeof(uint32_t *), hipMemcpyHostToDevice, b->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(b->group_words, gwords.data(), b->groups_pad * 4, hipMemcpyHostToDevice, b->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+        return check_launch("batch metadata upload");
+    return MICKEY_OK;
+}
+
+void destroy(mickey_batch *b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    if (b->dmem) (void)hipFree(b->dmem);
+    if (b->host_status) (void)hipHostFree(b->host_status);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+mickey_batch *mickey_batch_create(size_t max_requests, void *hip_stream)
+{
+    if (max_requests == 0 || max_requests > ((size_t)1 << 30)) {
+        fail(MICKEY_EINVAL, "mickey_batch_create: max_requests must be in 1..2^30");
+        return nullptr;
+    }
+    mickey_batch *b = new (std::nothrow) mickey_batch();
+    if (!b) {
+        fail(MICKEY_ENOMEM, "mickey_batch_create: host allocation failed");
+        return nullptr;
+    }
+    b->max_req = max_requests;
+    const size_t groups = (max_requests + 31) / 32;
+    b->max_groups_pad = (groups + 63) / 64 * 64;
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&b->stream) != hipSuccess) {
+            delete b;
+            fail(MICKEY_EDEVICE, "mickey_batch_create: cannot create a stream");
+            return nullptr;
+        }
+        b->own_stream = true;
+    }
+    const size_t slots = b->max_groups_pad * 32;
+    const size_t bytes = slots * (4 + sizeof(uint32_t *) + 4) + b->max_groups_pad * 4 + 256 +
+                         (size_t)(kInputPlanes + kMaskPlanes) * b->max_groups_pad * 4;
+    if (hipMalloc(&b->dmem, bytes) != hipSuccess ||
+        hipHostMalloc((void **)&b->host_status, 4, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        destroy(b);
+        fail(MICKEY_ENOMEM, "mickey_batch_create: cannot allocate %zu bytes", bytes);
+        return nullptr;
+    }
+    char *p = (char *)b->dmem;
+    b->lane_out = (uint32_t **)p;
+    p += slots * sizeof(uint32_t *);
+    b->order = (uint32_t *)p;
+    p += slots * 4;
+    b->lane_words = (uint32_t *)p;
+    p += slots * 4;
+    b->group_words = (uint32_t *)p;
+    p += b->max_groups_pad * 4;
+    b->counter = (uint32_t *)p;  // counter and status share one 256-byte line
+    b->status = b->counter + 1;
+    p += 256;
+    b->in_planes = (uint32_t *)p;
+    p += (size_t)kInputPlanes * b->max_groups_pad * 4;
+    b->mask_planes = (uint32_t *)p;
+    ok();
+    return b;
+}
+
+int mickey_batch_set(mickey_batch *b, const uint8_t *keys, const uint8_t *ivs, const uint8_t *iv_bits,
+                     const uint64_t *nbits, uint32_t *const *outs, size_t nreq)
+{
+    if (!b) return fail(MICKEY_EINVAL, "mickey_batch_set: NULL batch");
+    if (nreq == 0 || nreq > b->max_req)
+        return fail(MICKEY_EINVAL, "mickey_batch_set: %zu requests (capacity %zu)", nreq, b->max_req);
+    if (!keys || !ivs || !nbits || !outs) return fail(MICKEY_EINVAL, "mickey_batch_set: NULL argument");
+    for (size_t r = 0; r < nreq; r++) {
+        if (nbits[r] % 32 != 0) return fail(MICKEY_EINVAL, "request %zu: nbits must be a multiple of 32", r);
+        if (nbits[r] > kMaxBatchBits) return fail(MICKEY_ERANGE, "request %zu: more than 2^37 bits", r);
+        if (nbits[r] && !outs[r]) return fail(MICKEY_EINVAL, "request %zu: NULL output", r);
+    }
+    if (iv_bits) {  // validate the IV lengths once, here, so that runs never fail on them
+        if (hipMemsetAsync(b->status, 0, 4, b->stream) != hipSuccess) return check_launch("hipMemsetAsync");
+        hipLaunchKernelGGL(check_iv_bits_kernel, dim3((unsigned)((nreq + 255) / 256)), dim3(256), 0, b->stream,
+                           iv_bits, (uint32_t)nreq, b->status);
+        if (hipMemcpyAsync(b->host_status, b->status, 4, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+            hipStreamSynchronize(b->stream) != hipSuccess)
+            return check_launch("IV length check");
+        if (*b->host_status) return fail(MICKEY_EINVAL, "mickey_batch_set: an IV length exceeds 80 bits");
+    }
+    b->keys = keys;
+    b->ivs = ivs;
+    b->iv_bits = iv_bits;
+    b->nreq = nreq;
+    b->ngroups = (nreq + 31) / 32;
+    b->groups_pad = (b->ngroups + 63) / 64 * 64;
+    b->ntasks = b->groups_pad / 64;
+    b->nbits.assign(nbits, nbits + nreq);
+    b->outs.assign(outs, outs + nreq);
+    // longest first; ties keep request order
+    std::vector<uint32_t> idx(nreq);
+    std::iota(idx.begin(), idx.end(), 0u);
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t c) { return nbits[a] > nbits[c]; });
+    b->host_order.assign(b->groups_pad * 32, kNoRequest);
+    std::copy(idx.begin(), idx.end(), b->host_order.begin());
+    if (hipMemcpyAsync(b->order, b->host_order.data(), b->host_order.size() * 4, hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess)
+        return check_launch("order upload");
+    int rc = upload_meta(b, b->nbits, b->outs);
+    if (rc != MICKEY_OK) return rc;
+    rc = capture(b);
+    return rc == MICKEY_OK ? ok() : rc;
+}
+
+int mickey_batch_run(mickey_batch *b)
+{
+    if (!b) return fail(MICKEY_EINVAL, "mickey_batch_run: NULL batch");
+    if (!b->exec) return fail(MICKEY_EINVAL, "mickey_batch_run: no requests set");
+    hipError_t e = hipGraphLaunch(b->exec, b->stream);
+    if (e != hipSuccess) return fail(MICKEY_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+    return ok();
+}
+
+int mickey_batch_sync(mickey_batch *b)
+{
+    if (!b) return fail(MICKEY_EINVAL, "mickey_batch_sync: NULL batch");
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return fail(MICKEY_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    return ok();
+}
+
+void *mickey_batch_stream(const mickey_batch *b) { return b ? (void *)b->stream : nullptr; }
+
+int mickey_batch_set_params(mickey_batch *b, int unroll, int waves_per_block)
+{
+    if (!b) return fail(MICKEY_EINVAL, "mickey_batch_set_params: NULL batch");
+    const int u = unroll ? unroll : b->unroll, w = waves_per_block ? waves_per_block : b->wpb;
+    if (!find_variant(u, w))
+        return fail(MICKEY_EINVAL, "mickey_batch_set_params: unroll %d / %d waves per block not built", u, w);
+    b->unroll = u;
+    b->wpb = w;
+    if (b->nreq) {
+        int rc = capture(b);
+        if (rc != MICKEY_OK) return rc;
+    }
+    return ok();
+}
+
+int mickey_batch_get_params(const mickey_batch *b, int *unroll, int *waves_per_block)
+{
+    if (!b) return fail(MICKEY_EINVAL, "mickey_batch_get_params: NULL batch");
+    if (unroll) *unroll = b->unroll;
+    if (waves_per_block) *waves_per_block = b->wpb;
+    return ok();
+}
+
+int mickey_batch_autotune(mickey_batch *b, uint64_t cap_bits, const char *cache_path)
+{
+    if (!b) return fail(MICKEY_EINVAL, "mickey_batch_autotune: NULL batch");
+    if (!b->nreq) return fail(MICKEY_EINVAL, "mickey_batch_autotune: no requests set");
+    if (cap_bits < 32 || cap_bits % 32) return fail(MICKEY_EINVAL, "mickey_batch_autotune: cap must be k*32, k>0");
+    // signature of the tuning problem: architecture, request count, capped length mix
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    const char *arch = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.gcnArchName : "unknown";
+    uint64_t capped_total = 0, capped_max = 0;
+    for (uint64_t nb : b->nbits) {
+        capped_total += std::min(nb, cap_bits);
+        capped_max = std::max(capped_max, std::min(nb, cap_bits));
+    }
+    char sig[256];
+    snprintf(sig, sizeof sig, "%s/nreq=%zu/cap=%llu/total=%llu/max=%llu", arch, b->nreq, (unsigned long long)cap_bits,
+             (unsigned long long)capped_total, (unsigned long long)capped_max);
+    if (cache_path) {
+        if (FILE *f = fopen(cache_path, "r")) {
+            char buf[4096];
+            const size_t len = fread(buf, 1, sizeof buf - 1, f);
+            fclose(f);
+            buf[len] = 0;
+            int u = 0, w = 0;
+            const char *ps = strstr(buf, "\"signature\": \"");
+            const char *pu = strstr(buf, "\"unroll\": ");
+            const char *pw = strstr(buf, "\"waves_per_block\": ");
+            if (ps && pu && pw && strncmp(ps + 14, sig, strlen(sig)) == 0 && ps[14 + strlen(sig)] == '"' &&
+                sscanf(pu + 10, "%d", &u) == 1 && sscanf(pw + 19, "%d", &w) == 1 && find_variant(u, w))
+                return mickey_batch_set_params(b, u, w);
+        }
+    }
+    // scratch outputs for the capped run
+    std::vector<uint64_t> capped(b->nreq);
+    size_t words = 0;
+    for (size_t r = 0; r < b->nreq; r++) {
+        capped[r] = std::min(b->nbits[r], cap_bits);
+        words += capped[r] / 32;
+    }
+    uint32_t *scratch = nullptr;
+    if (hipMalloc(&scratch, std::max<size_t>(words, 1) * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MICKEY_ENOMEM, "mickey_batch_autotune: cannot allocate %zu bytes of scratch", words * 4);
+    }
+    std::vector<uint32_t *> souts(b->nreq);
+    for (size_t r = 0, w = 0; r < b->nreq; r++) {
+        souts[r] = scratch + w;
+        w += capped[r] / 32;
+    }
+    int rc = upload_meta(b, capped, souts);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == MICKEY_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = check_launch("hipEventCreate");
+    float best_ms = 0;
+    const Variant *best = nullptr;
+    std::string timings;
+    for (const Variant &v : kVariants) {
+        if (rc != MICKEY_OK) break;
+        rc = enqueue(b, v);  // warm-up (code load)
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2 && rc == MICKEY_OK; rep++) {
+            (void)hipEventRecord(e0, b->stream);
+            rc = enqueue(b, v);
+            (void)hipEventRecord(e1, b->stream);
+            if (rc == MICKEY_OK && hipEventSynchronize(e1) == hipSuccess) {
+                float t = 0;
+                (void)hipEventElapsedTime(&t, e0, e1);
+                ms = std::min(ms, t);
+            } else if (rc == MICKEY_OK) {
+                rc = check_launch("autotune timing");
+            }
+        }
+        if (rc != MICKEY_OK) break;
+        char item[64];
+        snprintf(item, sizeof item, "%s\"u%dw%d\": %.4f", timings.empty() ? "" : ", ", v.unroll, v.wpb, ms);
+        timings += item;
+        if (!best || ms < best_ms) {
+            best = &v;
+            best_ms = ms;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipFree(scratch);
+    const int rc2 = upload_meta(b, b->nbits, b->outs);  // restore the real outputs
+    if (rc != MICKEY_OK) return rc;
+    if (rc2 != MICKEY_OK) return rc2;
+    if (cache_path) {
+        if (FILE *f = fopen(cache_path, "w")) {
+            fprintf(f,
+                    "{\"signature\": \"%s\", \"unroll\": %d, \"waves_per_block\": %d, \"word_bits\": 32, "
+                    "\"best_ms\": %.4f, \"timings_ms\": {%s}}\n",
+                    sig, best->unroll, best->wpb, best_ms, timings.c_str());
+            fclose(f);
+        }
+    }
+    return mickey_batch_set_params(b, best->unroll, best->wpb);
+}
+
+void mickey_batch_free(mickey_batch *b) { destroy(b); }
+
+}  // extern "C"

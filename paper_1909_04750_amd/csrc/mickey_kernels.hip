@@ -9,152 +9,28 @@
 // Execution: one lane owns one 32-instance slice (K=1) or two adjacent slices (K=2)
 // and keeps its 200 state words in VGPRs for the whole call; one wave64 block per 64
 // lanes; no LDS except the row-major transpose staging.
-#include "mickey_bitslice.h"
+#include "mickey_device.h"
+#include "mickey_host.h"
 
 #include <hip/hip_runtime.h>
 
-#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
 
-#include "../../include/mickey.h"
-
 using namespace mickey;
+using namespace mickey_host;
 
 namespace {
 
-constexpr int kUnroll = 4;       // clocks per loop iteration of the generate kernels
-constexpr int kInitClocks = 260; // 80 IV slots + 80 key bits + 100 preclocks
-constexpr int kInputPlanes = 160;
-constexpr int kMaskPlanes = 96;  // clocks 0..95 (lanes can only idle before clock 80)
+constexpr int kUnroll = 4;  // clocks per loop iteration of the generate kernels
 
 // ------------------------------------------------------------------------ kernels
 
-// 32x32 bit transpose: on return a[r] bit c equals the input a[c] bit r.
-__device__ __forceinline__ void transpose32(uint32_t (&a)[32])
-{
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        if (i & 16) continue;
-        const uint32_t x = a[i], y = a[i + 16];
-        a[i] = (x & 0x0000FFFFu) | (y << 16);
-        a[i + 16] = (x >> 16) | (y & 0xFFFF0000u);
-    }
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        if (i & 8) continue;
-        const uint32_t x = a[i], y = a[i + 8];
-        a[i] = __builtin_amdgcn_bitop3_b32(x, y << 8, 0xFF00FF00u, (TA & ~TC) | (TB & TC));
-        a[i + 8] = __builtin_amdgcn_bitop3_b32(y, x >> 8, 0x00FF00FFu, (TA & ~TC) | (TB & TC));
-    }
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        if (i & 4) continue;
-        const uint32_t x = a[i], y = a[i + 4];
-        a[i] = __builtin_amdgcn_bitop3_b32(x, y << 4, 0xF0F0F0F0u, (TA & ~TC) | (TB & TC));
-        a[i + 4] = __builtin_amdgcn_bitop3_b32(y, x >> 4, 0x0F0F0F0Fu, (TA & ~TC) | (TB & TC));
-    }
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        if (i & 2) continue;
-        const uint32_t x = a[i], y = a[i + 2];
-        a[i] = __builtin_amdgcn_bitop3_b32(x, y << 2, 0xCCCCCCCCu, (TA & ~TC) | (TB & TC));
-        a[i + 2] = __builtin_amdgcn_bitop3_b32(y, x >> 2, 0x33333333u, (TA & ~TC) | (TB & TC));
-    }
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        if (i & 1) continue;
-        const uint32_t x = a[i], y = a[i + 1];
-        a[i] = __builtin_amdgcn_bitop3_b32(x, y << 1, 0xAAAAAAAAu, (TA & ~TC) | (TB & TC));
-        a[i + 1] = __builtin_amdgcn_bitop3_b32(y, x >> 1, 0x55555555u, (TA & ~TC) | (TB & TC));
-    }
-}
-
-// a1: input staging (the bitsliced input handler of Sec. IV-D).  Instance i with IV
-// length L idles for d = 80 - L clocks and then takes its L IV bits (MSB first), so the
-// key always enters at clock 80 in every lane: its input string is the 160-bit number
-// (ivL << 80) | key read MSB first (ivL = the L-bit IV), and its "started" string is
-// d zeros then ones.  A block of 256 instances (8 slices) writes these strings as
-// 32-bit chunks to LDS; then one wave turns each (slice, chunk) into 32 bit-planes with
-// an in-register 32x32 bit transpose and stores them.
-template <bool MASKED>
-__global__ __launch_bounds__(256) void stage_kernel(const uint8_t *__restrict__ keys,
-                                                    const uint8_t *__restrict__ ivs,
-                                                    const uint8_t *__restrict__ iv_bits, uint32_t n,
-                                                    uint32_t nslices, uint32_t *__restrict__ in_planes,
-                                                    uint32_t *__restrict__ mask_planes,
-                                                    uint32_t *__restrict__ status)
-{
-    constexpr int kChunks = kInputPlanes / 32, kMaskChunks = kMaskPlanes / 32;
-    __shared__ uint32_t chunk[kChunks + kMaskChunks][256];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t i = blockIdx.x * 256u + tid;
-    uint64_t kh = 0, ih = 0;
-    uint32_t kl = 0, il = 0, L = 80;
-    if (i < n) {
-        const uint8_t *k = keys + 10ull * i;
-        const uint8_t *v = ivs + 10ull * i;
-#pragma unroll
-        for (int b = 0; b < 8; b++) {
-            kh = (kh << 8) | k[b];
-            ih = (ih << 8) | v[b];
-        }
-        kl = ((uint32_t)k[8] << 8) | k[9];
-        il = ((uint32_t)v[8] << 8) | v[9];
-        if (MASKED) {
-            L = iv_bits[i];
-            if (L > 80u) {
-                atomicOr(status, 1u);
-                L = 80u;
-            }
-        }
-    }
-    typedef unsigned __int128 u128;
-    const u128 key80 = ((u128)kh << 16) | kl;
-    const u128 iv80 = ((u128)ih << 16) | il;
-    const u128 ivL = L ? (iv80 >> (80u - L)) : (u128)0;
-    const u128 lo = key80 | (ivL << 80);  // bits 0..127 of the input string
-    chunk[0][tid] = (uint32_t)(ivL >> 48);  // bits 159..128: clocks 0..31, MSB first
-    chunk[1][tid] = (uint32_t)(lo >> 96);
-    chunk[2][tid] = (uint32_t)(lo >> 64);
-    chunk[3][tid] = (uint32_t)(lo >> 32);
-    chunk[4][tid] = (uint32_t)lo;
-    if (MASKED) {
-        const uint32_t d = 80u - L;  // clocks before this lane starts
-#pragma unroll
-        for (int c = 0; c < kMaskChunks; c++) {
-            const uint32_t first = 32u * c;  // "started" bit of clock first+b is (first+b >= d)
-            chunk[kChunks + c][tid] = d <= first ? 0xFFFFFFFFu : (d >= first + 32u ? 0u : (0xFFFFFFFFu >> (d - first)));
-        }
-    }
-    __syncthreads();
-    constexpr int kTasks = 8 * (kChunks + (MASKED ? kMaskChunks : 0));
-    static_assert(kTasks <= 64, "one wave does the transposes");
-    if (tid >= (uint32_t)kTasks) return;
-    const uint32_t sl = tid & 7u, c = tid >> 3;
-    const uint32_t slice = blockIdx.x * 8u + sl;
-    if (slice >= nslices) return;
-    uint32_t a[32];
-#pragma unroll
-    for (int l = 0; l < 32; l++) a[l] = chunk[c][32u * sl + l];
-    transpose32(a);  // a[r] bit l = chunk word of instance l, bit r = clock 32c' + 31 - r
-    uint32_t *dst = c < (uint32_t)kChunks ? in_planes + (size_t)(32u * c) * nslices
-                                          : mask_planes + (size_t)(32u * (c - kChunks)) * nslices;
-#pragma unroll
-    for (int r = 0; r < 32; r++) dst[(size_t)(31 - r) * nslices + slice] = a[r];
-}
-
-__device__ __forceinline__ uint32_t ld_plane(const uint32_t *base, size_t pitch, uint32_t t, uint32_t voff)
-{
-    return *(const uint32_t *)((const char *)base + (size_t)t * pitch + voff);
-}
-
-// a2: initialisation.  One lane per slice; R = S = 0 then 260 mixing clocks.  With
-// MASKED, lanes whose IV is shorter than 80 bits stay at the zero state until their
-// first IV bit (only needed when some IV length differs from 80).
+// a2: initialisation.  One lane per slice; R = S = 0 then 260 mixing clocks, and the
+// registers are stored as the state planes.
 template <bool MASKED>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void init_kernel(
     const uint32_t *__restrict__ in_planes, const uint32_t *__restrict__ mask_planes,
@@ -163,90 +39,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     const uint32_t g = blockIdx.x * 64u + threadIdx.x;
     if (g >= nslices) return;
     const size_t pitch = (size_t)nslices * 4u;
-    uint32_t voff = g * 4u;
+    const uint32_t voff = g * 4u;
     Regs<1> x;
-#pragma unroll
-    for (int j = 0; j < 100; j++) {
-        x.r[j].w[0] = 0u;
-        x.s[j].w[0] = 0u;
-    }
-    const Word<1> ones = {{0xFFFFFFFFu}};
-    // IV part: clocks 0..79
-    for (uint32_t t = 0; t < 80u; t += kUnroll) {
-        Word<1> in[kUnroll], m[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; u++) {
-            in[u].w[0] = ld_plane(in_planes, pitch, t + u, voff);
-            m[u].w[0] = MASKED ? ld_plane(mask_planes, pitch, t + u, voff) : 0xFFFFFFFFu;
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; u++) clock_mix<1, MASKED>(x, in[u], m[u]);
-    }
-    // key part: clocks 80..159
-    for (uint32_t t = 80u; t < 160u; t += kUnroll) {
-        Word<1> in[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; u++) in[u].w[0] = ld_plane(in_planes, pitch, t + u, voff);
-#pragma unroll
-        for (int u = 0; u < kUnroll; u++) clock_mix<1, false>(x, in[u], ones);
-    }
-    // preclocks: 100 clocks with input 0
-    const Word<1> zero = {{0u}};
-    for (uint32_t t = 160u; t < (uint32_t)kInitClocks; t += kUnroll) {
-#pragma unroll
-        for (int u = 0; u < kUnroll; u++) clock_mix<1, false>(x, zero, ones);
-    }
-    asm volatile("" : "+v"(voff));
-#pragma unroll
-    for (int j = 0; j < 100; j++) {
-        *(uint32_t *)((char *)state + (size_t)j * pitch + voff) = x.r[j].w[0];
-        *(uint32_t *)((char *)state + (size_t)(100 + j) * pitch + voff) = x.s[j].w[0];
-    }
-}
-
-template <int K>
-__device__ __forceinline__ Word<K> ld_word(const char *p)
-{
-    Word<K> v;
-    if constexpr (K == 1) {
-        v.w[0] = *(const uint32_t *)p;
-    } else {
-        const uint2 q = *(const uint2 *)p;
-        v.w[0] = q.x;
-        v.w[1] = q.y;
-    }
-    return v;
-}
-
-template <int K>
-__device__ __forceinline__ void st_word(char *p, const Word<K> &v)
-{
-    if constexpr (K == 1) {
-        *(uint32_t *)p = v.w[0];
-    } else {
-        *(uint2 *)p = make_uint2(v.w[0], v.w[1]);
-    }
-}
-
-template <int K>
-__device__ __forceinline__ void load_state(Regs<K> &x, const uint32_t *state, size_t pitch, uint32_t voff)
-{
-#pragma unroll
-    for (int j = 0; j < 100; j++) {
-        x.r[j] = ld_word<K>((const char *)state + (size_t)j * pitch + voff);
-        x.s[j] = ld_word<K>((const char *)state + (size_t)(100 + j) * pitch + voff);
-    }
-}
-
-template <int K>
-__device__ __forceinline__ void store_state(const Regs<K> &x, uint32_t *state, size_t pitch, uint32_t voff)
-{
-    asm volatile("" : "+v"(voff));  // keep the load addresses from living across the loop
-#pragma unroll
-    for (int j = 0; j < 100; j++) {
-        st_word<K>((char *)state + (size_t)j * pitch + voff, x.r[j]);
-        st_word<K>((char *)state + (size_t)(100 + j) * pitch + voff, x.s[j]);
-    }
+    init_clocks<MASKED, kUnroll>(x, in_planes, mask_planes, pitch, voff);
+    store_state<1>(x, state, pitch, voff);
 }
 
 template <int K>
@@ -292,10 +88,9 @@ gen_bitsliced_kernel(uint32_t *__restrict__ state, uint32_t ngroups, uint32_t pi
     store_state<K>(x, state, pitch, voff);
 }
 
-// a3 + a5 + a6: keystream clocks with delivery as per-instance row-major words.  Each
-// 32 clocks a lane has 32 keystream words (one bit per instance); they are staged in
-// LDS (8 KB per wave), transposed in registers so that word l holds 32 consecutive
-// bits of instance 32g+l (first bit in the MSB), and stored as u32 and/or exact f32.
+// a3 + a5 + a6: keystream clocks with delivery as per-instance row-major words: every
+// 32 clocks each lane turns its 32 keystream words into one word per instance and
+// stores it as u32 and/or exact f32 ((w >> 8) * 2^-24).
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void gen_rowmajor_kernel(
     uint32_t *__restrict__ state, uint32_t nslices, uint32_t n, uint64_t nwords, uint32_t *__restrict__ out_u32,
     float *__restrict__ out_f32)
@@ -303,36 +98,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     __shared__ uint32_t zbuf[32][64];
     const uint32_t tid = threadIdx.x;
     const uint32_t g = blockIdx.x * 64u + tid;
-    if (g >= nslices) return;  // whole waves only: nslices is a multiple of 2, blocks of 64
+    if (g >= nslices) return;  // no barriers below: each lane only touches its LDS column
     const size_t pitch = (size_t)nslices * 4u;
     const uint32_t voff = g * 4u;
     Regs<1> x;
     load_state<1>(x, state, pitch, voff);
-    const size_t row_bytes = (size_t)nwords * 4u;
     const uint32_t first = g * 32u;
     const uint32_t valid = n > first ? (n - first < 32u ? n - first : 32u) : 0u;
+    uint32_t *ou = out_u32 ? out_u32 + (size_t)first * nwords : nullptr;
+    float *of = out_f32 ? out_f32 + (size_t)first * nwords : nullptr;
     for (uint64_t j = 0; j < nwords; j++) {
-        for (int b0 = 0; b0 < 32; b0 += kUnroll) {
-#pragma unroll
-            for (int u = 0; u < kUnroll; u++) {
-                // reversed row order: after the transpose, bit 31-b holds clock b
-                zbuf[31 - (b0 + u)][tid] = (x.r[0] ^ x.s[0]).w[0];
-                clock_gen<1>(x);
-            }
-        }
-        uint32_t a[32];
-#pragma unroll
-        for (int b = 0; b < 32; b++) a[b] = zbuf[b][tid];
-        transpose32(a);
-        const size_t col = (size_t)j * 4u;
-#pragma unroll
-        for (int l = 0; l < 32; l++) {
+        rowmajor_block<kUnroll>(x, zbuf, tid, [&](int l, uint32_t w) {
             if ((uint32_t)l < valid) {
-                const size_t off = (size_t)(first + l) * row_bytes + col;
-                if (out_u32) *(uint32_t *)((char *)out_u32 + off) = a[l];
-                if (out_f32) *(float *)((char *)out_f32 + off) = (float)(a[l] >> 8) * 0x1p-24f;
+                const size_t off = (size_t)l * nwords + j;
+                if (ou) ou[off] = w;
+                if (of) of[off] = (float)(w >> 8) * 0x1p-24f;
             }
-        }
+        });
     }
     store_state<1>(x, state, pitch, voff);
 }
@@ -396,7 +178,7 @@ struct mickey_state {
     int device;
 };
 
-namespace {
+namespace mickey_host {
 
 thread_local int g_err = MICKEY_OK;
 thread_local char g_msg[256] = "";
@@ -425,7 +207,16 @@ int check_launch(const char *what)
     return MICKEY_OK;
 }
 
-size_t pad64(size_t n) { return (n + 63) / 64 * 64; }
+void prefix_error(const char *prefix)
+{
+    char msg[sizeof g_msg];
+    memcpy(msg, g_msg, sizeof msg);
+    snprintf(g_msg, sizeof g_msg, "%s: %s", prefix, msg);
+}
+
+}  // namespace mickey_host
+
+namespace {
 
 // Largest instance count the 32-bit indexing of the kernels supports.
 constexpr size_t kMaxInstances = (size_t)1 << 31;
@@ -441,11 +232,11 @@ int run_init(mickey_state *st, const uint8_t *keys, const uint8_t *ivs, const ui
     if (hipMemsetAsync(status, 0, 4, st->stream) != hipSuccess) return check_launch("hipMemsetAsync");
     const dim3 sgrid((unsigned)((st->n_pad + 255) / 256));
     if (iv_bits)
-        hipLaunchKernelGGL(stage_kernel<true>, sgrid, dim3(256), 0, st->stream, keys, ivs, iv_bits, (uint32_t)st->n,
-                           (uint32_t)st->nslices, in_planes, mask_planes, status);
+        hipLaunchKernelGGL((stage_kernel<true, false>), sgrid, dim3(256), 0, st->stream, keys, ivs, iv_bits,
+                           nullptr, (uint32_t)st->n, (uint32_t)st->nslices, in_planes, mask_planes, status);
     else
-        hipLaunchKernelGGL(stage_kernel<false>, sgrid, dim3(256), 0, st->stream, keys, ivs, iv_bits,
-                           (uint32_t)st->n, (uint32_t)st->nslices, in_planes, mask_planes, status);
+        hipLaunchKernelGGL((stage_kernel<false, false>), sgrid, dim3(256), 0, st->stream, keys, ivs, iv_bits,
+                           nullptr, (uint32_t)st->n, (uint32_t)st->nslices, in_planes, mask_planes, status);
     int rc = check_launch("stage_kernel");
     if (rc != MICKEY_OK) return rc;
     const dim3 grid((unsigned)((st->nslices + 63) / 64));
@@ -510,12 +301,8 @@ mickey_state *init_impl(const uint8_t *keys, const uint8_t *ivs, const uint8_t *
     }
     int rc = run_init(st, keys, ivs, iv_bits);
     if (rc != MICKEY_OK) {
-        const int code = g_err;
-        char msg[sizeof g_msg];
-        memcpy(msg, g_msg, sizeof msg);
         destroy(st);
-        g_err = code;
-        snprintf(g_msg, sizeof g_msg, "mickey_init: %s", msg);
+        prefix_error("mickey_init");
         return nullptr;
     }
     ok();

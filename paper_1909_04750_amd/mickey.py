@@ -19,6 +19,8 @@ EXPORTED = [
     "mickey_free", "mickey_set_stream", "mickey_set_word_bits", "mickey_num_instances",
     "mickey_bits_generated", "mickey_plane_pitch", "mickey_state_export", "mickey_state_import",
     "mickey_sync", "mickey_last_error", "mickey_last_error_message", "mickey_ops_per_clock",
+    "mickey_batch_create", "mickey_batch_set", "mickey_batch_run", "mickey_batch_sync", "mickey_batch_stream",
+    "mickey_batch_set_params", "mickey_batch_get_params", "mickey_batch_autotune", "mickey_batch_free",
 ]
 
 _lib = None
@@ -73,6 +75,23 @@ def load_library():
     L.mickey_last_error_message.restype = ctypes.c_char_p
     L.mickey_ops_per_clock.argtypes = []
     L.mickey_ops_per_clock.restype = i
+    L.mickey_batch_create.argtypes = [sz, vp]
+    L.mickey_batch_create.restype = vp
+    L.mickey_batch_set.argtypes = [vp, vp, vp, vp, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_void_p), sz]
+    L.mickey_batch_set.restype = i
+    for name in ("mickey_batch_run", "mickey_batch_sync"):
+        getattr(L, name).argtypes = [vp]
+        getattr(L, name).restype = i
+    L.mickey_batch_stream.argtypes = [vp]
+    L.mickey_batch_stream.restype = vp
+    L.mickey_batch_set_params.argtypes = [vp, i, i]
+    L.mickey_batch_set_params.restype = i
+    L.mickey_batch_get_params.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
+    L.mickey_batch_get_params.restype = i
+    L.mickey_batch_autotune.argtypes = [vp, u64, ctypes.c_char_p]
+    L.mickey_batch_autotune.restype = i
+    L.mickey_batch_free.argtypes = [vp]
+    L.mickey_batch_free.restype = None
     _lib = L
     return L
 
@@ -212,3 +231,67 @@ class Mickey:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Batch:
+    """mickey_batch: many fresh requests in one persistent, graph-captured launch."""
+
+    def __init__(self, max_requests: int, stream=None):
+        L = load_library()
+        h = L.mickey_batch_create(int(max_requests), None if stream is None else ctypes.c_void_p(stream.cuda_stream))
+        if not h:
+            raise MickeyError(L.mickey_last_error(), L.mickey_last_error_message().decode())
+        self._h = ctypes.c_void_p(h)
+        self.max_requests = int(max_requests)
+        self._keep = None
+
+    @property
+    def stream_handle(self) -> int:
+        return int(load_library().mickey_batch_stream(self._h) or 0)
+
+    def set(self, keys, ivs, iv_bits, nbits, out_ptrs) -> None:
+        """keys/ivs uint8 [nreq,10] and iv_bits uint8 [nreq] (or None) CUDA tensors;
+        nbits: host sequence of lengths (multiples of 32); out_ptrs: host sequence of
+        device addresses (int) receiving nbits/32 row-major words each."""
+        import numpy as np
+        n = int(keys.shape[0])
+        nb = np.ascontiguousarray(np.asarray(nbits, dtype=np.uint64))
+        op = np.ascontiguousarray(np.asarray(out_ptrs, dtype=np.uint64))
+        assert nb.shape == (n,) and op.shape == (n,)
+        kp = _dev_ptr(keys, "keys", 10 * n)
+        vp = _dev_ptr(ivs, "ivs", 10 * n)
+        bp = None if iv_bits is None else _dev_ptr(iv_bits, "iv_bits", n)
+        self._keep = (keys, ivs, iv_bits)  # device inputs must outlive the runs
+        _check(load_library().mickey_batch_set(
+            self._h, kp, vp, bp, nb.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+            op.ctypes.data_as(ctypes.POINTER(ctypes.c_void_p)), n))
+
+    def run(self) -> None:
+        _check(load_library().mickey_batch_run(self._h))
+
+    def sync(self) -> None:
+        _check(load_library().mickey_batch_sync(self._h))
+
+    def set_params(self, unroll: int = 0, waves_per_block: int = 0) -> None:
+        _check(load_library().mickey_batch_set_params(self._h, int(unroll), int(waves_per_block)))
+
+    def get_params(self):
+        u, w = ctypes.c_int(0), ctypes.c_int(0)
+        _check(load_library().mickey_batch_get_params(self._h, ctypes.byref(u), ctypes.byref(w)))
+        return u.value, w.value
+
+    def autotune(self, cap_bits: int, cache_path=None):
+        _check(load_library().mickey_batch_autotune(
+            self._h, int(cap_bits), None if cache_path is None else str(cache_path).encode()))
+        return self.get_params()
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load_library().mickey_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

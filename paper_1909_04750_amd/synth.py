@@ -64,6 +64,25 @@ def iv_lengths_mixed(seed: int, n: int, idx=None) -> np.ndarray:
     return np.array([0, 32, 64, 80], dtype=np.uint8)[sel]
 
 
+def batch_requests(seed: int, n: int, max_log2: float = 24.0, min_log2: float = 8.0):
+    """Fresh requests for the batched workload: (keys, ivs, iv_bits, nbits).
+
+    keys/ivs as keys_ivs(seed, n); IV length of request i = ((draw(4n+i) >> 32) * 81) >> 32
+    (uniform in 0..80); keystream length = 32 * floor(2^(min + (max-min)*u) / 32) with
+    u = (draw(5n+i) >> 11) * 2^-53, i.e. log-uniform between 2^min and 2^max bits,
+    rounded down to whole 32-bit words.  The float power is evaluated here only, and
+    both the GPU run and the oracle consume the resulting integer lengths.
+    """
+    keys, ivs = keys_ivs(seed, n)
+    i = np.arange(n, dtype=np.uint64)
+    x = draws(seed, np.uint64(4 * n) + i)
+    with np.errstate(over="ignore"):
+        ivb = (((x >> np.uint64(32)) * np.uint64(81)) >> np.uint64(32)).astype(np.uint8)
+    u = (draws(seed, np.uint64(5 * n) + i) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    nbits = (32 * np.floor(2.0 ** (min_log2 + (max_log2 - min_log2) * u) / 32)).astype(np.uint64)
+    return keys, ivs, ivb, nbits
+
+
 def workload(name: str):
     """Named workloads: (seed, n instances, keystream bits per instance, IV-length recipe)."""
     table = {
@@ -73,6 +92,8 @@ def workload(name: str):
         "plain-4m": (2, 1 << 22, 8192, "80"),
         # 2^20 instances, IV lengths in {0,32,64,80}, 65536 bits each, row-major u32+f32
         "rowmajor-1m": (3, 1 << 20, 65536, "mixed"),
+        # 10,000 fresh requests, IV lengths 0..80, lengths log-uniform in [2^8, 2^24) bits
+        "batch-10k": (4, 10000, None, "batch"),
     }
     return table[name]
 

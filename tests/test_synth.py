@@ -31,3 +31,16 @@ def test_mixed_iv_lengths():
     vals, counts = np.unique(L, return_counts=True)
     assert vals.tolist() == [0, 32, 64, 80]
     assert (abs(counts - (1 << 12)) < 400).all()
+
+
+def test_batch_recipe_ranges():
+    keys, ivs, ivb, nbits = synth.batch_requests(4, 10000)
+    assert keys.shape == (10000, 10) and ivs.shape == (10000, 10)
+    assert ivb.min() == 0 and ivb.max() == 80
+    assert (nbits % 32 == 0).all()
+    assert nbits.min() >= 256 and nbits.max() < (1 << 24)
+    # log-uniform: about a quarter of the requests above 2^20 bits
+    frac = (nbits >= (1 << 20)).mean()
+    assert 0.2 < frac < 0.3
+    k2, v2, b2, n2 = synth.batch_requests(4, 10000, max_log2=16.0)
+    assert (k2 == keys).all() and (b2 == ivb).all() and n2.max() < (1 << 16)
