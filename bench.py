@@ -69,6 +69,106 @@ def cpu_baseline(keys, ivs, nbits, gpu_sample_bits, sample_idx, threads):
     }
 
 
+def bench_rowmajor(torch, mickey, synth, reps: int = 3):
+    """2^20 instances, IV lengths in {0,32,64,80}, 65536 bits each, in-kernel transpose to
+    row-major u32 plus exact f32 (16 GiB of output)."""
+    seed, n, nbits, _ = synth.workload("rowmajor-1m")
+    keys, ivs, ivb = synth.workload_inputs("rowmajor-1m")
+    dk, dv, db = (torch.from_numpy(a).cuda() for a in (keys, ivs, ivb))
+    stream = torch.cuda.current_stream()
+    m = mickey.Mickey(dk, dv, db, stream=stream)
+    u = torch.empty((n, nbits // 32), dtype=torch.int32, device="cuda")
+    f = torch.empty((n, nbits // 32), dtype=torch.float32, device="cuda")
+    m.generate_rowmajor(nbits, u, f)  # warm-up
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_init, t_gen = [], []
+    for _ in range(reps):
+        ev[0].record(stream)
+        m.rekey(dk, dv, db)
+        ev[1].record(stream)
+        m.generate_rowmajor(nbits, u, f)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        t_init.append(ev[0].elapsed_time(ev[1]))
+        t_gen.append(ev[1].elapsed_time(ev[2]))
+    m.close()
+    step = float(np.mean(t_init) + np.mean(t_gen))
+    bits = n * nbits
+    print("# rowmajor-1m: init %.3f ms, generate %.3f ms" % (np.mean(t_init), np.mean(t_gen)), file=sys.stderr,
+          flush=True)
+    return {"workload": "2^20 instances, IV lengths {0,32,64,80}, 65536 bits each, row-major u32 + f32",
+            "gbit_s": round(bits / (step * 1e-3) / 1e9, 3), "init_ms": round(float(np.mean(t_init)), 4),
+            "generate_ms": round(float(np.mean(t_gen)), 4),
+            "generate_gbit_s": round(bits / (np.mean(t_gen) * 1e-3) / 1e9, 3),
+            "waves": n // 32 // 64, "note": "2^20 instances fill 512 of 2048 wave slots at 32 instances per lane"}
+
+
+def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 12):
+    """10,000 fresh requests (seed 4): IV lengths 0..80, lengths log-uniform in
+    [2^8, 2^24) bits; one persistent work-queue launch replayed from a HIP graph,
+    autotuned; compared with per-request plain launches (timed on a sample of requests
+    and extrapolated linearly in length) and with the critical-path bound."""
+    import tempfile
+    keys, ivs, ivb, nbits = synth.batch_requests(4, 10000)
+    n = len(nbits)
+    dk, dv, db = (torch.from_numpy(a).cuda() for a in (keys, ivs, ivb))
+    words = (nbits // 32).astype(np.int64)
+    offs = np.concatenate([[0], np.cumsum(words)])
+    arena = torch.empty(int(offs[-1]), dtype=torch.int32, device="cuda")
+    ptrs = [arena.data_ptr() + 4 * int(o) for o in offs[:-1]]
+    b = mickey.Batch(n)
+    b.set(dk, dv, db, nbits, ptrs)
+    with tempfile.TemporaryDirectory() as td:
+        params = b.autotune(tune_cap_bits, os.path.join(td, "batch_tune.json"))
+        tune = json.load(open(os.path.join(td, "batch_tune.json")))
+    bs = torch.cuda.ExternalStream(b.stream_handle)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(bs)
+    b.run()
+    e1.record(bs)
+    b.sync()
+    batch_ms = e0.elapsed_time(e1)
+    b.close()
+    del arena
+    total_bits = int(nbits.sum())
+    print("# batch-10k: %.1f ms (params %s)" % (batch_ms, params), file=sys.stderr, flush=True)
+    # per-request plain launches (mickey_init with n = 1, then row-major generate) on a
+    # sample of requests up to 2^16 bits, fitted as a + b * nbits
+    stream = torch.cuda.current_stream()
+    order = np.argsort(nbits.astype(np.int64))
+    short = order[nbits[order] <= (1 << 16)]
+    pick = short[np.linspace(0, len(short) - 1, nsample).astype(int)]
+    ts, ls = [], []
+    out1 = torch.empty(1 << 11, dtype=torch.int32, device="cuda")
+    for k, i in enumerate(pick):
+        e0.record(stream)
+        m = mickey.Mickey(dk[i:i + 1], dv[i:i + 1], db[i:i + 1], stream=stream)
+        m.generate(int(nbits[i]), mickey.ROWMAJOR_U32, out1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        m.close()
+        if k:  # first one warms up
+            ts.append(e0.elapsed_time(e1))
+            ls.append(float(nbits[i]))
+    slope, icpt = np.polyfit(np.array(ls), np.array(ts), 1)
+    serial_ms = float(np.sum(icpt + slope * nbits.astype(np.float64)))
+    lmax = int(nbits.max())
+    bound_ms = float(icpt + slope * lmax)  # one lane running the longest request alone
+    return {"workload": "10,000 fresh requests (splitmix64 seed 4), IV lengths 0..80, lengths log-uniform in "
+                        "[2^8, 2^24) bits, row-major u32 outputs, one persistent launch (HIP graph)",
+            "requests": n, "total_bits": total_bits, "batch_ms": round(batch_ms, 2),
+            "gbit_s": round(total_bits / (batch_ms * 1e-3) / 1e9, 3),
+            "params": {"unroll": params[0], "waves_per_block": params[1], "word_bits": 32,
+                       "tune_timings_ms": tune.get("timings_ms")},
+            "critical_path": {"longest_bits": lmax, "bound_ms": round(bound_ms, 2),
+                              "batch_over_bound": round(batch_ms / bound_ms, 4),
+                              "clock_ns_single_lane": round(slope * 1e6, 2)},
+            "per_request_plain": {"sampled": len(ts), "fit_ms": [round(icpt, 4), round(slope * 1e6, 4)],
+                                  "fit_units": ["ms", "ns per bit"], "extrapolated_serial_ms": round(serial_ms, 1),
+                                  "batch_speedup": round(serial_ms / batch_ms, 1)}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +177,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-word64", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--no-rowmajor", action="store_true", help="skip the row-major 2^20 x 65536 measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 10,000-request batched measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the instances are independent, so more GPUs "
@@ -195,6 +297,12 @@ def main() -> int:
         res["cpu_baseline"] = cpu_baseline(keys, ivs, nbits, gpu_bits, sample_idx, threads)
 
     m.close()
+    del out
+    torch.cuda.empty_cache()
+    if not args.no_rowmajor:
+        res["rowmajor_1m"] = bench_rowmajor(torch, mickey, synth)
+    if not args.no_batch:
+        res["batch_10k"] = bench_batch(torch, mickey, synth)
     print(json.dumps(res), flush=True)
     return 0
 

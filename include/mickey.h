@@ -183,6 +183,64 @@ int mickey_batch_autotune(mickey_batch *b, uint64_t cap_bits, const char *cache_
 
 void mickey_batch_free(mickey_batch *b);
 
+/* ---------------------------------------------------------------------------------
+ * Serving: resident generator states, requests that resume them, continuous batching.
+ *
+ * The server keeps every state of an initialised mickey_state resident in HBM (25 bytes
+ * each, the mickey_state_export layout) and owns `nslices` bitsliced slots of 32 lane
+ * bits, a quantum length and an output budget.  mickey_server_step() admits waiting
+ * requests in arrival order into free lane bits while their whole output fits in the
+ * budget (one request per state at a time, so requests on a state run in arrival
+ * order), gathers their states, and runs one quantum on every occupied slot; requests
+ * that arrive while others run join at the next quantum.  A request's keystream
+ * continues its state exactly where the previous request on that state stopped, and
+ * its state is written back at the exact clock where it ends.
+ */
+typedef struct mickey_server mickey_server;
+
+/* Create a server over the n instances of `init` (their current registers and bit
+ * counter become the resident states 0..n-1; `init` may be freed afterwards).
+ *   nslices         slot capacity in slices (32 concurrent requests each; rounded up to
+ *                   a multiple of 64)
+ *   quantum_clocks  clocks per scheduling step, a multiple of 32
+ *   budget_bytes    device memory for outputs of admitted requests
+ *   hip_stream      stream of the server's work (NULL: the server creates one) */
+mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, uint32_t quantum_clocks,
+                                    uint64_t budget_bytes, void *hip_stream);
+
+/* Queue a request: resume state `state_id` for nbits keystream bits (a positive multiple
+ * of 32).  Returns the request id (>= 0) or a negative error code. */
+int64_t mickey_server_submit(mickey_server *s, uint32_t state_id, uint64_t nbits);
+
+/* One scheduling step: admissions, gathers, one quantum, retirement.  Synchronises the
+ * server's stream (the host learns which requests finished). */
+int mickey_server_step(mickey_server *s);
+
+/* Ids of requests completed since the last call (at most cap); returns the count. */
+int64_t mickey_server_poll(mickey_server *s, uint64_t *ids, size_t cap);
+
+/* A completed request's output (device, nbits/32 words in the MICKEY_ROWMAJOR_U32 layout
+ * of one instance) and its arrival / admission / completion times (ns, steady clock).
+ * MICKEY_ERANGE (and *out = NULL) if it was refused for passing 2^40 bits. */
+int mickey_server_result(const mickey_server *s, uint64_t id, uint32_t **out, uint64_t times_ns[3]);
+
+/* Copy the first nwords words of a completed request's output into dst (device);
+ * synchronous. */
+int mickey_server_copy(const mickey_server *s, uint64_t id, uint32_t *dst, uint64_t nwords);
+
+/* Return a completed request's output space to the budget (its words become invalid). */
+int mickey_server_release(mickey_server *s, uint64_t id);
+
+/* [0] waiting, [1] running, [2] admitted, [3] finished, [4] steps, [5] quantum time in
+ * ns, [6] keystream bits delivered, [7] free budget in 32-bit words. */
+int mickey_server_stats(const mickey_server *s, uint64_t out[8]);
+
+/* Device pointer to resident state `state_id` (25 bytes) and its bit counter. */
+int mickey_server_state(const mickey_server *s, uint32_t state_id, const uint8_t **packed, uint64_t *bits);
+
+void *mickey_server_stream(const mickey_server *s);
+void mickey_server_free(mickey_server *s);
+
 int mickey_last_error(void);
 const char *mickey_last_error_message(void);
 

@@ -1,0 +1,498 @@
+// Served generation: a pool of resident generator states in HBM, requests that resume
+// one state each for a keystream of a given length, and continuous batching.
+//
+// Resident states are kept packed (25 bytes each: r_0..r_99 s_0..s_99, MSB first, the
+// mickey_state_export layout).  The server owns a fixed set of bitsliced slots (slices
+// of 32 lane bits, state planes as in the plain path).  Each scheduling step
+//   1. retires requests that completed in the last quantum (their state was written
+//      back to the pool by the kernel at the exact clock where the request ended),
+//   2. admits waiting requests, in arrival order, into free lane bits while the output
+//      budget allows (a request reserves its whole output; a state runs at most one
+//      request at a time, so requests on one state run in arrival order),
+//   3. gathers the admitted states into their lane bits, and
+//   4. runs one quantum of Q clocks on every occupied slice, writing each request's
+//      keystream as row-major words (MICKEY_ROWMAJOR_U32 layout) into its output.
+// Requests that arrive while others run join at the next quantum, next to them.
+#include "mickey_device.h"
+#include "mickey_host.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <vector>
+
+using namespace mickey;
+using namespace mickey_host;
+
+namespace {
+
+constexpr int kServeUnroll = 4;
+
+// One admission: lane bit `lane` (slice lane/32, bit lane%32) takes resident state `sid`.
+struct Admit {
+    uint32_t lane;
+    uint32_t sid;
+    uint32_t words;
+    uint32_t pad;
+    uint32_t *out;
+};
+
+// Gather: write the packed state `sid` into bit lane%32 of word lane/32 of every plane,
+// and set the lane's output metadata.  Lanes of one slice may be admitted in the same
+// launch, so the plane words are updated with atomics.
+__global__ __launch_bounds__(256) void admit_kernel(const Admit *__restrict__ adm, uint32_t nadm,
+                                                    const uint8_t *__restrict__ pool, uint32_t *__restrict__ planes,
+                                                    uint32_t nslices, uint32_t **lane_out, uint32_t *lane_left,
+                                                    uint32_t *lane_sid)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nadm) return;
+    const Admit a = adm[k];
+    const uint32_t g = a.lane >> 5, bit = 1u << (a.lane & 31u);
+    const uint8_t *p = pool + 25ull * a.sid;
+    for (int j = 0; j < 200; j++) {
+        uint32_t *w = planes + (size_t)j * nslices + g;
+        if ((p[j >> 3] >> (7 - (j & 7))) & 1u)
+            atomicOr(w, bit);
+        else
+            atomicAnd(w, ~bit);
+    }
+    lane_out[a.lane] = a.out;
+    lane_left[a.lane] = a.words;
+    lane_sid[a.lane] = a.sid;
+}
+
+// Pack bit l of the 200 state words into 25 bytes at dst (MSB first).
+__device__ __forceinline__ void write_back_lane(const Regs<1> &x, uint32_t l, uint8_t *dst)
+{
+    uint32_t w[7];
+#pragma unroll
+    for (int k = 0; k < 7; k++) w[k] = 0u;
+#pragma unroll
+    for (int j = 0; j < 200; j++) {
+        const uint32_t v = j < 100 ? x.r[j].w[0] : x.s[j - 100].w[0];
+        w[j >> 5] |= ((v >> l) & 1u) << (31 - (j & 31));
+    }
+#pragma unroll
+    for (int b = 0; b < 25; b++) dst[b] = (uint8_t)(w[b >> 2] >> (24 - 8 * (b & 3)));
+}
+
+// One quantum of nblocks*32 clocks on every slice with an occupied lane bit.  Per-lane
+// output pointers and remaining word counts live in LDS for the quantum.  When a lane's
+// request ends at the end of a block, its state is packed back into the pool there and
+// the lane is appended to the completion list.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void quantum_kernel(
+    uint32_t *__restrict__ planes, uint32_t nslices, uint32_t nblocks, uint32_t **lane_out,
+    uint32_t *__restrict__ lane_left, const uint32_t *__restrict__ lane_sid, uint8_t *__restrict__ pool,
+    uint32_t *__restrict__ done_list, uint32_t *__restrict__ done_count)
+{
+    __shared__ uint32_t zbuf[32][64];
+    __shared__ uint32_t *s_out[32][64];
+    __shared__ uint32_t s_left[32][64];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t g = blockIdx.x * 64u + tid;
+    if (g >= nslices) return;  // no barriers: each lane touches only its own LDS columns
+    uint32_t active = 0;
+    for (int l = 0; l < 32; l++) {
+        const uint32_t left = lane_left[g * 32u + l];
+        s_left[l][tid] = left;
+        s_out[l][tid] = lane_out[g * 32u + l];
+        active |= (left ? 1u : 0u) << l;
+    }
+    if (!active) return;
+    const size_t pitch = (size_t)nslices * 4u;
+    const uint32_t voff = g * 4u;
+    Regs<1> x;
+    load_state<1>(x, planes, pitch, voff);
+    for (uint32_t blk = 0; blk < nblocks && active; blk++) {
+        uint32_t finished = 0;
+        rowmajor_block<kServeUnroll>(x, zbuf, tid, [&](int l, uint32_t w) {
+            if ((active >> l) & 1u) {
+                uint32_t *o = s_out[l][tid];
+                *o = w;
+                s_out[l][tid] = o + 1;
+                const uint32_t left = s_left[l][tid] - 1u;
+                s_left[l][tid] = left;
+                if (!left) finished |= 1u << l;
+            }
+        });
+        if (finished) {
+            for (uint32_t l = 0; l < 32; l++) {
+                if ((finished >> l) & 1u) {
+                    write_back_lane(x, l, pool + 25ull * lane_sid[g * 32u + l]);
+                    done_list[atomicAdd(done_count, 1u)] = g * 32u + l;
+                }
+            }
+            active &= ~finished;
+        }
+    }
+    store_state<1>(x, planes, pitch, voff);
+    for (int l = 0; l < 32; l++) {
+        lane_left[g * 32u + l] = s_left[l][tid];
+        lane_out[g * 32u + l] = s_out[l][tid];
+    }
+}
+
+struct Request {
+    uint64_t id;
+    uint32_t sid;
+    uint64_t nbits;
+    uint64_t arrival_ns;
+    uint64_t admit_ns = 0, done_ns = 0;
+    uint32_t lane = kNoRequest;
+    size_t out_off = 0;  // word offset in the arena
+    bool done = false;
+    bool released = false;
+};
+
+// First-fit allocator over the output arena, in 32-bit words.
+struct Arena {
+    size_t capacity = 0;
+    std::map<size_t, size_t> free_by_off;  // offset -> length
+    void reset(size_t words)
+    {
+        capacity = words;
+        free_by_off.clear();
+        free_by_off[0] = words;
+    }
+    bool alloc(size_t words, size_t *off)
+    {
+        for (auto it = free_by_off.begin(); it != free_by_off.end(); ++it) {
+            if (it->second >= words) {
+                *off = it->first;
+                const size_t rest = it->second - words, start = it->first + words;
+                free_by_off.erase(it);
+                if (rest) free_by_off[start] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t words)
+    {
+        auto it = free_by_off.emplace(off, words).first;
+        auto nx = std::next(it);
+        if (nx != free_by_off.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_by_off.erase(nx);
+        }
+        if (it != free_by_off.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_by_off.erase(it);
+            }
+        }
+    }
+};
+
+uint64_t now_ns()
+{
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+}  // namespace
+
+struct mickey_server {
+    size_t nstates = 0, nslices = 0, nlanes = 0;
+    uint32_t qblocks = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint8_t *pool = nullptr;   // [nstates][25]
+    uint32_t *planes = nullptr;
+    uint32_t **lane_out = nullptr;
+    uint32_t *lane_left = nullptr, *lane_sid = nullptr;
+    uint32_t *done_list = nullptr, *done_count = nullptr;
+    Admit *dadm = nullptr;
+    uint32_t *arena = nullptr;
+    Arena alloc;
+    // host side
+    Admit *hadm = nullptr;        // pinned
+    uint32_t *hdone = nullptr;    // pinned: count then list
+    std::vector<uint64_t> state_bits;
+    std::vector<uint8_t> state_busy;
+    std::vector<uint32_t> free_lanes;
+    std::deque<uint64_t> waiting;  // request ids in arrival order
+    std::vector<Request> reqs;     // by id
+    std::vector<uint64_t> lane_req;
+    std::vector<uint64_t> completed;  // not yet reported
+    uint64_t steps = 0, quanta_ns = 0, admitted = 0, finished = 0, bits_done = 0;
+};
+
+namespace {
+
+void destroy(mickey_server *s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (void *p : {(void *)s->pool, (void *)s->planes, (void *)s->lane_out, (void *)s->lane_left,
+                    (void *)s->lane_sid, (void *)s->done_list, (void *)s->dadm, (void *)s->arena})
+        if (p) (void)hipFree(p);
+    if (s->hadm) (void)hipHostFree(s->hadm);
+    if (s->hdone) (void)hipHostFree(s->hdone);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, uint32_t quantum_clocks,
+                                    uint64_t budget_bytes, void *hip_stream)
+{
+    if (!init) {
+        fail(MICKEY_EINVAL, "mickey_server_create: NULL initial states");
+        return nullptr;
+    }
+    if (nslices == 0 || nslices > ((size_t)1 << 24) || quantum_clocks == 0 || quantum_clocks % 32 ||
+        budget_bytes < 4) {
+        fail(MICKEY_EINVAL, "mickey_server_create: bad slots, quantum (multiple of 32) or budget");
+        return nullptr;
+    }
+    mickey_server *s = new (std::nothrow) mickey_server();
+    if (!s) {
+        fail(MICKEY_ENOMEM, "mickey_server_create: host allocation failed");
+        return nullptr;
+    }
+    s->nstates = mickey_num_instances(init);
+    s->nslices = (nslices + 63) / 64 * 64;
+    s->nlanes = s->nslices * 32;
+    s->qblocks = quantum_clocks / 32;
+    if (hip_stream) {
+        s->stream = (hipStream_t)hip_stream;
+    } else if (hipStreamCreate(&s->stream) == hipSuccess) {
+        s->own_stream = true;
+    } else {
+        delete s;
+        fail(MICKEY_EDEVICE, "mickey_server_create: cannot create a stream");
+        return nullptr;
+    }
+    const size_t budget_words = budget_bytes / 4;
+    bool okm = hipMalloc(&s->pool, 25 * s->nstates) == hipSuccess &&
+               hipMalloc(&s->planes, 200 * s->nslices * 4) == hipSuccess &&
+               hipMalloc(&s->lane_out, s->nlanes * sizeof(uint32_t *)) == hipSuccess &&
+               hipMalloc(&s->lane_left, s->nlanes * 4) == hipSuccess &&
+               hipMalloc(&s->lane_sid, s->nlanes * 4) == hipSuccess &&
+               hipMalloc(&s->done_list, (s->nlanes + 64) * 4) == hipSuccess &&
+               hipMalloc(&s->dadm, s->nlanes * sizeof(Admit)) == hipSuccess &&
+               hipMalloc(&s->arena, budget_words * 4) == hipSuccess &&
+               hipHostMalloc((void **)&s->hadm, s->nlanes * sizeof(Admit), hipHostMallocDefault) == hipSuccess &&
+               hipHostMalloc((void **)&s->hdone, (s->nlanes + 64) * 4, hipHostMallocDefault) == hipSuccess;
+    if (!okm) {
+        (void)hipGetLastError();
+        destroy(s);
+        fail(MICKEY_ENOMEM, "mickey_server_create: cannot allocate the pool, slots or %llu-byte budget",
+             (unsigned long long)budget_bytes);
+        return nullptr;
+    }
+    s->done_count = s->done_list + s->nlanes;
+    // the initial states: the registers of the given initialised instances
+    int rc = mickey_state_export(init, s->pool, nullptr);
+    if (rc == MICKEY_OK && (hipMemsetAsync(s->lane_left, 0, s->nlanes * 4) != hipSuccess ||
+                            hipMemsetAsync(s->planes, 0, 200 * s->nslices * 4) != hipSuccess ||
+                            hipDeviceSynchronize() != hipSuccess))
+        rc = check_launch("mickey_server_create");
+    if (rc != MICKEY_OK) {
+        destroy(s);
+        prefix_error("mickey_server_create");
+        return nullptr;
+    }
+    s->alloc.reset(budget_words);
+    s->state_bits.assign(s->nstates, mickey_bits_generated(init));
+    s->state_busy.assign(s->nstates, 0);
+    s->free_lanes.resize(s->nlanes);
+    for (size_t i = 0; i < s->nlanes; i++) s->free_lanes[i] = (uint32_t)(s->nlanes - 1 - i);
+    s->lane_req.assign(s->nlanes, ~0ull);
+    ok();
+    return s;
+}
+
+int64_t mickey_server_submit(mickey_server *s, uint32_t state_id, uint64_t nbits)
+{
+    if (!s) return fail(MICKEY_EINVAL, "mickey_server_submit: NULL server");
+    if (state_id >= s->nstates) return fail(MICKEY_EINVAL, "mickey_server_submit: state %u out of range", state_id);
+    if (nbits == 0 || nbits % 32 || nbits / 32 > s->alloc.capacity)
+        return fail(MICKEY_EINVAL, "mickey_server_submit: nbits must be k*32, 0 < k, within the budget");
+    Request r;
+    r.id = s->reqs.size();
+    r.sid = state_id;
+    r.nbits = nbits;
+    r.arrival_ns = now_ns();
+    s->reqs.push_back(r);
+    s->waiting.push_back(r.id);
+    ok();
+    return (int64_t)r.id;
+}
+
+int mickey_server_step(mickey_server *s)
+{
+    if (!s) return fail(MICKEY_EINVAL, "mickey_server_step: NULL server");
+    // 2. admit in arrival order
+    uint32_t nadm = 0;
+    const uint64_t t_admit = now_ns();
+    for (auto it = s->waiting.begin(); it != s->waiting.end() && !s->free_lanes.empty();) {
+        Request &r = s->reqs[*it];
+        if (s->state_busy[r.sid]) {  // an earlier request on this state is still running
+            ++it;
+            continue;
+        }
+        if (s->state_bits[r.sid] + r.nbits > MICKEY_MAX_BITS_PER_IV) {  // 2^40 per key/IV pair
+            r.done = true;
+            r.done_ns = t_admit;
+            r.lane = kNoRequest;
+            s->completed.push_back(r.id);
+            it = s->waiting.erase(it);
+            continue;
+        }
+        size_t off = 0;
+        if (!s->alloc.alloc(r.nbits / 32, &off)) break;  // budget full: keep arrival order
+        const uint32_t lane = s->free_lanes.back();
+        s->free_lanes.pop_back();
+        r.lane = lane;
+        r.out_off = off;
+        r.admit_ns = t_admit;
+        s->state_busy[r.sid] = 1;
+        s->lane_req[lane] = r.id;
+        s->hadm[nadm++] = Admit{lane, r.sid, (uint32_t)(r.nbits / 32), 0u, s->arena + off};
+        s->admitted++;
+        it = s->waiting.erase(it);
+    }
+    // 3. gather
+    if (nadm) {
+        if (hipMemcpyAsync(s->dadm, s->hadm, nadm * sizeof(Admit), hipMemcpyHostToDevice, s->stream) != hipSuccess)
+            return check_launch("admission upload");
+        hipLaunchKernelGGL(admit_kernel, dim3((nadm + 255) / 256), dim3(256), 0, s->stream, s->dadm, nadm, s->pool,
+                           s->planes, (uint32_t)s->nslices, s->lane_out, s->lane_left, s->lane_sid);
+        int rc = check_launch("admit_kernel");
+        if (rc != MICKEY_OK) return rc;
+    }
+    // 4. one quantum
+    if (hipMemsetAsync(s->done_count, 0, 4, s->stream) != hipSuccess) return check_launch("hipMemsetAsync");
+    const uint64_t t0 = now_ns();
+    hipLaunchKernelGGL(quantum_kernel, dim3((unsigned)(s->nslices / 64)), dim3(64), 0, s->stream, s->planes,
+                       (uint32_t)s->nslices, s->qblocks, s->lane_out, s->lane_left, s->lane_sid, s->pool,
+                       s->done_list, s->done_count);
+    int rc = check_launch("quantum_kernel");
+    if (rc != MICKEY_OK) return rc;
+    if (hipMemcpyAsync(s->hdone, s->done_count, 4, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+        return check_launch("completion readback");
+    const uint32_t ndone = s->hdone[0];
+    if (ndone && (hipMemcpy(s->hdone + 1, s->done_list, ndone * 4, hipMemcpyDeviceToHost) != hipSuccess))
+        return check_launch("completion list");
+    const uint64_t t1 = now_ns();
+    s->quanta_ns += t1 - t0;
+    s->steps++;
+    // 1. retire (for the next step)
+    for (uint32_t k = 0; k < ndone; k++) {
+        const uint32_t lane = s->hdone[1 + k];
+        Request &r = s->reqs[s->lane_req[lane]];
+        r.done = true;
+        r.done_ns = t1;
+        s->state_bits[r.sid] += r.nbits;
+        s->state_busy[r.sid] = 0;
+        s->lane_req[lane] = ~0ull;
+        s->free_lanes.push_back(lane);
+        s->completed.push_back(r.id);
+        s->finished++;
+        s->bits_done += r.nbits;
+    }
+    return ok();
+}
+
+// Completed request ids since the last call (up to cap); returns how many were written.
+int64_t mickey_server_poll(mickey_server *s, uint64_t *ids, size_t cap)
+{
+    if (!s || (!ids && cap)) return fail(MICKEY_EINVAL, "mickey_server_poll: bad argument");
+    const size_t n = std::min(cap, s->completed.size());
+    std::copy(s->completed.begin(), s->completed.begin() + n, ids);
+    s->completed.erase(s->completed.begin(), s->completed.begin() + n);
+    ok();
+    return (int64_t)n;
+}
+
+// Result of a completed request: device pointer to its nbits/32 words (NULL if it was
+// rejected for passing 2^40 bits), its timestamps (ns, steady clock) and status.
+int mickey_server_result(const mickey_server *s, uint64_t id, uint32_t **out, uint64_t times_ns[3])
+{
+    if (!s || id >= s->reqs.size()) return fail(MICKEY_EINVAL, "mickey_server_result: unknown request");
+    const Request &r = s->reqs[id];
+    if (!r.done) return fail(MICKEY_EINVAL, "mickey_server_result: request %llu not complete", (unsigned long long)id);
+    if (r.released) return fail(MICKEY_EINVAL, "mickey_server_result: request %llu was released", (unsigned long long)id);
+    if (out) *out = r.lane == kNoRequest ? nullptr : s->arena + r.out_off;
+    if (times_ns) {
+        times_ns[0] = r.arrival_ns;
+        times_ns[1] = r.admit_ns;
+        times_ns[2] = r.done_ns;
+    }
+    if (r.lane == kNoRequest) return fail(MICKEY_ERANGE, "request %llu would pass 2^40 bits", (unsigned long long)id);
+    return ok();
+}
+
+// Give a completed request's output space back to the budget.
+int mickey_server_release(mickey_server *s, uint64_t id)
+{
+    if (!s || id >= s->reqs.size()) return fail(MICKEY_EINVAL, "mickey_server_release: unknown request");
+    Request &r = s->reqs[id];
+    if (!r.done || r.lane == kNoRequest || r.released)
+        return fail(MICKEY_EINVAL, "mickey_server_release: nothing to release");
+    s->alloc.release(r.out_off, r.nbits / 32);
+    r.released = true;
+    return ok();
+}
+
+// Counters: [0] waiting, [1] running, [2] admitted, [3] finished, [4] steps,
+// [5] total quantum time (ns), [6] keystream bits delivered, [7] free budget words.
+int mickey_server_stats(const mickey_server *s, uint64_t out[8])
+{
+    if (!s || !out) return fail(MICKEY_EINVAL, "mickey_server_stats: bad argument");
+    size_t freew = 0;
+    for (auto &kv : s->alloc.free_by_off) freew += kv.second;
+    out[0] = s->waiting.size();
+    out[1] = s->nlanes - s->free_lanes.size();
+    out[2] = s->admitted;
+    out[3] = s->finished;
+    out[4] = s->steps;
+    out[5] = s->quanta_ns;
+    out[6] = s->bits_done;
+    out[7] = freew;
+    return ok();
+}
+
+// Packed registers of resident state `sid` (25 bytes, device) and its bit counter.
+int mickey_server_state(const mickey_server *s, uint32_t sid, const uint8_t **packed, uint64_t *bits)
+{
+    if (!s || sid >= s->nstates) return fail(MICKEY_EINVAL, "mickey_server_state: bad state");
+    if (packed) *packed = s->pool + 25ull * sid;
+    if (bits) *bits = s->state_bits[sid];
+    return ok();
+}
+
+// Copy the first nwords words of a completed request's output into dst (device);
+// synchronous.
+int mickey_server_copy(const mickey_server *s, uint64_t id, uint32_t *dst, uint64_t nwords)
+{
+    uint32_t *src = nullptr;
+    int rc = mickey_server_result(s, id, &src, nullptr);
+    if (rc != MICKEY_OK) return rc;
+    if (!dst || nwords > s->reqs[id].nbits / 32) return fail(MICKEY_EINVAL, "mickey_server_copy: bad destination");
+    if (hipMemcpyAsync(dst, src, nwords * 4, hipMemcpyDeviceToDevice, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+        return check_launch("mickey_server_copy");
+    return ok();
+}
+
+void *mickey_server_stream(const mickey_server *s) { return s ? (void *)s->stream : nullptr; }
+
+void mickey_server_free(mickey_server *s) { destroy(s); }
+
+}  // extern "C"

@@ -21,6 +21,9 @@ EXPORTED = [
     "mickey_sync", "mickey_last_error", "mickey_last_error_message", "mickey_ops_per_clock",
     "mickey_batch_create", "mickey_batch_set", "mickey_batch_run", "mickey_batch_sync", "mickey_batch_stream",
     "mickey_batch_set_params", "mickey_batch_get_params", "mickey_batch_autotune", "mickey_batch_free",
+    "mickey_server_create", "mickey_server_submit", "mickey_server_step", "mickey_server_poll",
+    "mickey_server_result", "mickey_server_copy", "mickey_server_release", "mickey_server_stats",
+    "mickey_server_state", "mickey_server_stream", "mickey_server_free",
 ]
 
 _lib = None
@@ -92,6 +95,28 @@ def load_library():
     L.mickey_batch_autotune.restype = i
     L.mickey_batch_free.argtypes = [vp]
     L.mickey_batch_free.restype = None
+    L.mickey_server_create.argtypes = [vp, sz, ctypes.c_uint32, u64, vp]
+    L.mickey_server_create.restype = vp
+    L.mickey_server_submit.argtypes = [vp, ctypes.c_uint32, u64]
+    L.mickey_server_submit.restype = ctypes.c_int64
+    L.mickey_server_step.argtypes = [vp]
+    L.mickey_server_step.restype = i
+    L.mickey_server_poll.argtypes = [vp, ctypes.POINTER(u64), sz]
+    L.mickey_server_poll.restype = ctypes.c_int64
+    L.mickey_server_result.argtypes = [vp, u64, ctypes.POINTER(vp), ctypes.POINTER(u64)]
+    L.mickey_server_result.restype = i
+    L.mickey_server_copy.argtypes = [vp, u64, vp, u64]
+    L.mickey_server_copy.restype = i
+    L.mickey_server_release.argtypes = [vp, u64]
+    L.mickey_server_release.restype = i
+    L.mickey_server_stats.argtypes = [vp, ctypes.POINTER(u64)]
+    L.mickey_server_stats.restype = i
+    L.mickey_server_state.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(vp), ctypes.POINTER(u64)]
+    L.mickey_server_state.restype = i
+    L.mickey_server_stream.argtypes = [vp]
+    L.mickey_server_stream.restype = vp
+    L.mickey_server_free.argtypes = [vp]
+    L.mickey_server_free.restype = None
     _lib = L
     return L
 
@@ -288,6 +313,73 @@ class Batch:
     def close(self) -> None:
         if getattr(self, "_h", None):
             load_library().mickey_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """mickey_server: resident states, resumable requests, continuous batching."""
+
+    STAT_KEYS = ("waiting", "running", "admitted", "finished", "steps", "quantum_ns", "bits_delivered",
+                 "free_budget_words")
+
+    def __init__(self, init: "Mickey", nslices: int, quantum_clocks: int, budget_bytes: int, stream=None):
+        L = load_library()
+        h = L.mickey_server_create(init._h, int(nslices), int(quantum_clocks), int(budget_bytes),
+                                   None if stream is None else ctypes.c_void_p(stream.cuda_stream))
+        if not h:
+            raise MickeyError(L.mickey_last_error(), L.mickey_last_error_message().decode())
+        self._h = ctypes.c_void_p(h)
+        self.n = init.n
+
+    def submit(self, state_id: int, nbits: int) -> int:
+        r = load_library().mickey_server_submit(self._h, int(state_id), int(nbits))
+        if r < 0:
+            _check(int(r))
+        return int(r)
+
+    def step(self) -> None:
+        _check(load_library().mickey_server_step(self._h))
+
+    def poll(self, cap: int = 1 << 16):
+        buf = (ctypes.c_uint64 * cap)()
+        k = load_library().mickey_server_poll(self._h, buf, cap)
+        if k < 0:
+            _check(int(k))
+        return [int(buf[j]) for j in range(k)]
+
+    def times(self, rid: int):
+        """(arrival, admission, completion) in ns of the steady clock; raises MickeyError
+        with code ERANGE for a request refused at the 2^40-bit limit."""
+        t = (ctypes.c_uint64 * 3)()
+        p = ctypes.c_void_p()
+        _check(load_library().mickey_server_result(self._h, int(rid), ctypes.byref(p), t))
+        return int(t[0]), int(t[1]), int(t[2])
+
+    def copy(self, rid: int, dst, nwords: int) -> None:
+        _check(load_library().mickey_server_copy(self._h, int(rid), _dev_ptr(dst, "dst", 4 * nwords), int(nwords)))
+
+    def release(self, rid: int) -> None:
+        _check(load_library().mickey_server_release(self._h, int(rid)))
+
+    def stats(self) -> dict:
+        out = (ctypes.c_uint64 * 8)()
+        _check(load_library().mickey_server_stats(self._h, out))
+        return dict(zip(self.STAT_KEYS, [int(v) for v in out]))
+
+    def state_bits(self, sid: int) -> int:
+        b = ctypes.c_uint64()
+        _check(load_library().mickey_server_state(self._h, int(sid), None, ctypes.byref(b)))
+        return int(b.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load_library().mickey_server_free(self._h)
             self._h = None
 
     def __del__(self):
