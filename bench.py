@@ -169,6 +169,108 @@ def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 
                                   "batch_speedup": round(serial_ms / batch_ms, 1)}}
 
 
+def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, rate: float = 20000.0,
+                nstates: int = 10 ** 6, budget: int = 64 << 30, sat_bytes: int = 32 << 10, sat_seconds: float = 3.0):
+    """Served generation over 10^6 resident states (splitmix64 seed 5 keys and 80-bit
+    IVs, initialised).  Open loop: Poisson arrivals at `rate`/s for `duration` s, state
+    uniform, size log-uniform in [4 KiB, max_bytes]; latency = completion - scheduled
+    arrival.  Closed loop (saturation): every state keeps one sat_bytes request in flight
+    for sat_seconds; compared with the plain kernel on the same 10^6 instances."""
+    keys, ivs = synth.keys_ivs(5, nstates)
+    dk, dv = torch.from_numpy(keys).cuda(), torch.from_numpy(ivs).cuda()
+    init = mickey.Mickey(dk, dv)
+    init.sync()
+    out = {}
+    # -- open loop
+    t_arr, sids, nbits = synth.serve_requests(5, nstates, rate, duration, 4096, max_bytes)
+    n = len(t_arr)
+    srv = mickey.Server(init, nslices=2048, quantum_clocks=2048, budget_bytes=budget)
+    lat = np.zeros(n)
+    t0 = time.monotonic_ns()
+    i = done_n = 0
+    last_done = t0
+    while done_n < n:
+        now = (time.monotonic_ns() - t0) * 1e-9
+        k = int(np.searchsorted(t_arr, now, side="right"))
+        if k > i:
+            srv.submit_many(sids[i:k], nbits[i:k])  # ids are assigned in arrival order
+            i = k
+        srv.step()
+        ids = srv.poll()
+        if len(ids):
+            tm = srv.times_many(ids)
+            lat[ids] = (tm[:, 2].astype(np.float64) - t0) * 1e-9 - t_arr[ids]
+            last_done = max(last_done, int(tm[:, 2].max()))
+            srv.release_many(ids)
+            done_n += len(ids)
+        elif i == n and srv.stats()["running"] == 0 and srv.stats()["waiting"] == 0:
+            srv.wait()
+    st = srv.stats()
+    srv.close()
+    span = (last_done - t0) * 1e-9
+    total = int(nbits.sum())
+    out["open_loop"] = {
+        "workload": "10^6 resident states; Poisson arrivals %.0f/s for %.1f s; state uniform; size log-uniform "
+                    "4 KiB..%d KiB (configured range 4 KiB..64 MiB, cut for bench time); row-major u32 output; "
+                    "64 GiB output budget; 2048 slots x 32 lanes; quantum 2048 clocks" % (rate, duration, max_bytes >> 10),
+        "requests": n, "total_bits": total, "span_s": round(span, 3),
+        "served_gbit_s": round(total / span / 1e9, 3), "offered_gbit_s": round(total / duration / 1e9, 3),
+        "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
+                      "max": round(float(lat.max()), 4)},
+        "steps": st["steps"], "mean_quantum_ms": round(st["quantum_ns"] / max(st["steps"], 1) / 1e6, 3),
+    }
+    print("# serve open loop: %d requests, p50 %.3f s p99 %.3f s" % (n, out["open_loop"]["latency_s"]["p50"],
+          out["open_loop"]["latency_s"]["p99"]), file=sys.stderr, flush=True)
+    # -- closed loop: every state busy
+    sat_bits = 8 * sat_bytes
+    srv = mickey.Server(init, nslices=(nstates + 31) // 32, quantum_clocks=8192, budget_bytes=budget)
+    all_s = np.arange(nstates, dtype=np.uint32)
+    sid_of = list(all_s)
+    srv.submit_many(all_s, np.full(nstates, sat_bits, dtype=np.uint64))
+    t_start = time.monotonic_ns()
+    b0 = None
+    while True:
+        srv.step()
+        ids = srv.poll()
+        if len(ids):
+            srv.release_many(ids)
+            again = np.asarray([sid_of[j] for j in ids.tolist()], dtype=np.uint32)
+            sid_of.extend(again.tolist())
+            srv.submit_many(again, np.full(len(again), sat_bits, dtype=np.uint64))
+        el = (time.monotonic_ns() - t_start) * 1e-9
+        if b0 is None and el > 1.0:  # warm-up second
+            b0, tb0 = srv.stats()["bits_delivered"], time.monotonic_ns()
+        if b0 is not None and el > 1.0 + sat_seconds:
+            break
+    srv.wait()
+    b1, tb1 = srv.stats()["bits_delivered"], time.monotonic_ns()
+    st = srv.stats()
+    srv.close()
+    served = (b1 - b0) / ((tb1 - tb0) * 1e-9) / 1e9
+    # plain kernel on the same 10^6 instances, row-major, for the same per-instance length
+    stream = torch.cuda.current_stream()
+    buf = torch.empty((nstates, sat_bits // 32), dtype=torch.int32, device="cuda")
+    init.generate(sat_bits, mickey.ROWMAJOR_U32, buf)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    init.generate(sat_bits, mickey.ROWMAJOR_U32, buf)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain = nstates * sat_bits / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del buf
+    init.close()
+    out["closed_loop"] = {
+        "workload": "every one of the 10^6 states keeps one %d KiB request in flight (resubmitted on completion), "
+                    "%d slots, quantum 8192 clocks, measured over %.1f s after 1 s warm-up" % (
+                        sat_bytes >> 10, (nstates + 31) // 32, sat_seconds),
+        "served_gbit_s": round(served, 3), "plain_same_instances_gbit_s": round(plain, 3),
+        "served_over_plain": round(served / plain, 4), "steps": st["steps"],
+        "mean_quantum_ms": round(st["quantum_ns"] / max(st["steps"], 1) / 1e6, 3),
+    }
+    print("# serve closed loop: %.1f Gbit/s served vs %.1f plain" % (served, plain), file=sys.stderr, flush=True)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +281,9 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-rowmajor", action="store_true", help="skip the row-major 2^20 x 65536 measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 10,000-request batched measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served measurements")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="Poisson arrival window of the served run")
+    ap.add_argument("--serve-max-kib", type=int, default=256, help="largest served request (KiB)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the instances are independent, so more GPUs "
@@ -303,6 +408,8 @@ def main() -> int:
         res["rowmajor_1m"] = bench_rowmajor(torch, mickey, synth)
     if not args.no_batch:
         res["batch_10k"] = bench_batch(torch, mickey, synth)
+    if not args.no_serve:
+        res["serve"] = bench_serve(torch, mickey, synth, args.serve_seconds, args.serve_max_kib << 10)
     print(json.dumps(res), flush=True)
     return 0
 

@@ -212,9 +212,22 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
  * of 32).  Returns the request id (>= 0) or a negative error code. */
 int64_t mickey_server_submit(mickey_server *s, uint32_t state_id, uint64_t nbits);
 
-/* One scheduling step: admissions, gathers, one quantum, retirement.  Synchronises the
- * server's stream (the host learns which requests finished). */
+/* Batched forms: submit n requests (ids[k] gets the id or a negative code), release n
+ * completed requests, and read n completed requests' (arrival, admission, completion)
+ * times into out[3k..3k+2] (completion 0 for a request refused at 2^40 bits). */
+int mickey_server_submit_many(mickey_server *s, const uint32_t *sids, const uint64_t *nbits, size_t n,
+                              int64_t *ids);
+int mickey_server_release_many(mickey_server *s, const uint64_t *ids, size_t n);
+int mickey_server_times_many(const mickey_server *s, const uint64_t *ids, size_t n, uint64_t *out);
+
+/* One scheduling step: wait for the quantum launched by the previous step and retire
+ * the requests it completed, admit waiting requests and gather their states, then launch
+ * the next quantum and return without waiting for it (the caller's host work overlaps
+ * the GPU).  Does nothing on the GPU when no request is running or admitted. */
 int mickey_server_step(mickey_server *s);
+
+/* Wait for the in-flight quantum, if any, and retire its requests. */
+int mickey_server_wait(mickey_server *s);
 
 /* Ids of requests completed since the last call (at most cap); returns the count. */
 int64_t mickey_server_poll(mickey_server *s, uint64_t *ids, size_t cap);

@@ -215,8 +215,12 @@ struct mickey_server {
     uint32_t *arena = nullptr;
     Arena alloc;
     // host side
-    Admit *hadm = nullptr;        // pinned
-    uint32_t *hdone = nullptr;    // pinned: count then list
+    Admit *hadm = nullptr;          // pinned
+    uint32_t *hcount = nullptr;     // pinned: completions of the in-flight quantum
+    uint32_t *hlist = nullptr;      // pinned, mapped: the kernel appends completed lanes here
+    uint32_t *hlist_dev = nullptr;  // device view of hlist
+    bool inflight = false;
+    uint64_t launch_ns = 0;
     std::vector<uint64_t> state_bits;
     std::vector<uint8_t> state_busy;
     std::vector<uint32_t> free_lanes;
@@ -237,9 +241,42 @@ void destroy(mickey_server *s)
                     (void *)s->lane_sid, (void *)s->done_list, (void *)s->dadm, (void *)s->arena})
         if (p) (void)hipFree(p);
     if (s->hadm) (void)hipHostFree(s->hadm);
-    if (s->hdone) (void)hipHostFree(s->hdone);
+    if (s->hcount) (void)hipHostFree(s->hcount);
+    if (s->hlist) (void)hipHostFree(s->hlist);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
+}
+
+// Clear the completion counter (a kernel, so that the sequence stays capturable).
+__global__ void reset_count_kernel(uint32_t *c)
+{
+    if (threadIdx.x == 0) *c = 0u;
+}
+
+// Wait for the in-flight quantum (if any) and retire the requests it completed.
+int retire(mickey_server *s)
+{
+    if (!s->inflight) return MICKEY_OK;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    s->inflight = false;
+    if (e != hipSuccess) return fail(MICKEY_EDEVICE, "quantum: %s", hipGetErrorString(e));
+    const uint64_t t1 = now_ns();
+    s->quanta_ns += t1 - s->launch_ns;
+    const uint32_t ndone = *s->hcount;
+    for (uint32_t k = 0; k < ndone; k++) {
+        const uint32_t lane = s->hlist[k];
+        Request &r = s->reqs[s->lane_req[lane]];
+        r.done = true;
+        r.done_ns = t1;
+        s->state_bits[r.sid] += r.nbits;
+        s->state_busy[r.sid] = 0;
+        s->lane_req[lane] = ~0ull;
+        s->free_lanes.push_back(lane);
+        s->completed.push_back(r.id);
+        s->finished++;
+        s->bits_done += r.nbits;
+    }
+    return MICKEY_OK;
 }
 
 }  // namespace
@@ -282,11 +319,13 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
                hipMalloc(&s->lane_out, s->nlanes * sizeof(uint32_t *)) == hipSuccess &&
                hipMalloc(&s->lane_left, s->nlanes * 4) == hipSuccess &&
                hipMalloc(&s->lane_sid, s->nlanes * 4) == hipSuccess &&
-               hipMalloc(&s->done_list, (s->nlanes + 64) * 4) == hipSuccess &&
+               hipMalloc(&s->done_list, 256) == hipSuccess &&
                hipMalloc(&s->dadm, s->nlanes * sizeof(Admit)) == hipSuccess &&
                hipMalloc(&s->arena, budget_words * 4) == hipSuccess &&
                hipHostMalloc((void **)&s->hadm, s->nlanes * sizeof(Admit), hipHostMallocDefault) == hipSuccess &&
-               hipHostMalloc((void **)&s->hdone, (s->nlanes + 64) * 4, hipHostMallocDefault) == hipSuccess;
+               hipHostMalloc((void **)&s->hcount, 64, hipHostMallocDefault) == hipSuccess &&
+               hipHostMalloc((void **)&s->hlist, s->nlanes * 4, hipHostMallocMapped) == hipSuccess &&
+               hipHostGetDevicePointer((void **)&s->hlist_dev, s->hlist, 0) == hipSuccess;
     if (!okm) {
         (void)hipGetLastError();
         destroy(s);
@@ -294,7 +333,7 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
              (unsigned long long)budget_bytes);
         return nullptr;
     }
-    s->done_count = s->done_list + s->nlanes;
+    s->done_count = s->done_list;  // device word: completions of the in-flight quantum
     // the initial states: the registers of the given initialised instances
     int rc = mickey_state_export(init, s->pool, nullptr);
     if (rc == MICKEY_OK && (hipMemsetAsync(s->lane_left, 0, s->nlanes * 4) != hipSuccess ||
@@ -336,13 +375,18 @@ int64_t mickey_server_submit(mickey_server *s, uint32_t state_id, uint64_t nbits
 int mickey_server_step(mickey_server *s)
 {
     if (!s) return fail(MICKEY_EINVAL, "mickey_server_step: NULL server");
-    // 2. admit in arrival order
+    // 1. retire what the previous quantum completed
+    int rc = retire(s);
+    if (rc != MICKEY_OK) return rc;
+    // 2. admit in arrival order; requests on busy states keep their place
     uint32_t nadm = 0;
     const uint64_t t_admit = now_ns();
-    for (auto it = s->waiting.begin(); it != s->waiting.end() && !s->free_lanes.empty();) {
-        Request &r = s->reqs[*it];
-        if (s->state_busy[r.sid]) {  // an earlier request on this state is still running
-            ++it;
+    std::deque<uint64_t> keep;
+    bool full = false;
+    for (uint64_t id : s->waiting) {
+        Request &r = s->reqs[id];
+        if (full || s->state_busy[r.sid]) {
+            keep.push_back(id);
             continue;
         }
         if (s->state_bits[r.sid] + r.nbits > MICKEY_MAX_BITS_PER_IV) {  // 2^40 per key/IV pair
@@ -350,11 +394,14 @@ int mickey_server_step(mickey_server *s)
             r.done_ns = t_admit;
             r.lane = kNoRequest;
             s->completed.push_back(r.id);
-            it = s->waiting.erase(it);
             continue;
         }
         size_t off = 0;
-        if (!s->alloc.alloc(r.nbits / 32, &off)) break;  // budget full: keep arrival order
+        if (s->free_lanes.empty() || !s->alloc.alloc(r.nbits / 32, &off)) {  // slots or budget full
+            full = true;
+            keep.push_back(id);
+            continue;
+        }
         const uint32_t lane = s->free_lanes.back();
         s->free_lanes.pop_back();
         r.lane = lane;
@@ -364,47 +411,80 @@ int mickey_server_step(mickey_server *s)
         s->lane_req[lane] = r.id;
         s->hadm[nadm++] = Admit{lane, r.sid, (uint32_t)(r.nbits / 32), 0u, s->arena + off};
         s->admitted++;
-        it = s->waiting.erase(it);
     }
+    s->waiting.swap(keep);
     // 3. gather
     if (nadm) {
         if (hipMemcpyAsync(s->dadm, s->hadm, nadm * sizeof(Admit), hipMemcpyHostToDevice, s->stream) != hipSuccess)
             return check_launch("admission upload");
         hipLaunchKernelGGL(admit_kernel, dim3((nadm + 255) / 256), dim3(256), 0, s->stream, s->dadm, nadm, s->pool,
                            s->planes, (uint32_t)s->nslices, s->lane_out, s->lane_left, s->lane_sid);
-        int rc = check_launch("admit_kernel");
+        rc = check_launch("admit_kernel");
         if (rc != MICKEY_OK) return rc;
     }
-    // 4. one quantum
-    if (hipMemsetAsync(s->done_count, 0, 4, s->stream) != hipSuccess) return check_launch("hipMemsetAsync");
-    const uint64_t t0 = now_ns();
+    if (s->free_lanes.size() == s->nlanes) return ok();  // nothing to run
+    // 4. one quantum; the host learns its completions at the next step
+    hipLaunchKernelGGL(reset_count_kernel, dim3(1), dim3(64), 0, s->stream, s->done_count);
+    s->launch_ns = now_ns();
     hipLaunchKernelGGL(quantum_kernel, dim3((unsigned)(s->nslices / 64)), dim3(64), 0, s->stream, s->planes,
                        (uint32_t)s->nslices, s->qblocks, s->lane_out, s->lane_left, s->lane_sid, s->pool,
-                       s->done_list, s->done_count);
-    int rc = check_launch("quantum_kernel");
+                       s->hlist_dev, s->done_count);
+    rc = check_launch("quantum_kernel");
     if (rc != MICKEY_OK) return rc;
-    if (hipMemcpyAsync(s->hdone, s->done_count, 4, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
-        hipStreamSynchronize(s->stream) != hipSuccess)
-        return check_launch("completion readback");
-    const uint32_t ndone = s->hdone[0];
-    if (ndone && (hipMemcpy(s->hdone + 1, s->done_list, ndone * 4, hipMemcpyDeviceToHost) != hipSuccess))
-        return check_launch("completion list");
-    const uint64_t t1 = now_ns();
-    s->quanta_ns += t1 - t0;
+    if (hipMemcpyAsync(s->hcount, s->done_count, 4, hipMemcpyDeviceToHost, s->stream) != hipSuccess)
+        return check_launch("completion count");
+    s->inflight = true;
     s->steps++;
-    // 1. retire (for the next step)
-    for (uint32_t k = 0; k < ndone; k++) {
-        const uint32_t lane = s->hdone[1 + k];
-        Request &r = s->reqs[s->lane_req[lane]];
-        r.done = true;
-        r.done_ns = t1;
-        s->state_bits[r.sid] += r.nbits;
-        s->state_busy[r.sid] = 0;
-        s->lane_req[lane] = ~0ull;
-        s->free_lanes.push_back(lane);
-        s->completed.push_back(r.id);
-        s->finished++;
-        s->bits_done += r.nbits;
+    return ok();
+}
+
+// Wait for the in-flight quantum and retire its requests (no new work is started).
+int mickey_server_wait(mickey_server *s)
+{
+    if (!s) return fail(MICKEY_EINVAL, "mickey_server_wait: NULL server");
+    int rc = retire(s);
+    return rc == MICKEY_OK ? ok() : rc;
+}
+
+// Many submissions at once: ids[k] receives the id of (sids[k], nbits[k]), or a negative
+// error code for that entry.  Returns MICKEY_OK, or the first error code.
+int mickey_server_submit_many(mickey_server *s, const uint32_t *sids, const uint64_t *nbits, size_t n,
+                              int64_t *ids)
+{
+    if (!s || (n && (!sids || !nbits || !ids))) return fail(MICKEY_EINVAL, "mickey_server_submit_many: bad argument");
+    int first = MICKEY_OK;
+    for (size_t k = 0; k < n; k++) {
+        ids[k] = mickey_server_submit(s, sids[k], nbits[k]);
+        if (ids[k] < 0 && first == MICKEY_OK) first = (int)ids[k];
+    }
+    return first == MICKEY_OK ? ok() : first;
+}
+
+// Release many completed requests; returns MICKEY_OK or the first error code.
+int mickey_server_release_many(mickey_server *s, const uint64_t *ids, size_t n)
+{
+    if (!s || (n && !ids)) return fail(MICKEY_EINVAL, "mickey_server_release_many: bad argument");
+    int first = MICKEY_OK;
+    for (size_t k = 0; k < n; k++) {
+        const int rc = mickey_server_release(s, ids[k]);
+        if (rc != MICKEY_OK && first == MICKEY_OK) first = rc;
+    }
+    return first == MICKEY_OK ? ok() : first;
+}
+
+// Times of many completed requests: out[3k..3k+2] = arrival, admission, completion (ns);
+// refused requests get completion = 0.
+int mickey_server_times_many(const mickey_server *s, const uint64_t *ids, size_t n, uint64_t *out)
+{
+    if (!s || (n && (!ids || !out))) return fail(MICKEY_EINVAL, "mickey_server_times_many: bad argument");
+    for (size_t k = 0; k < n; k++) {
+        if (ids[k] >= s->reqs.size() || !s->reqs[ids[k]].done)
+            return fail(MICKEY_EINVAL, "mickey_server_times_many: request %llu not complete",
+                        (unsigned long long)ids[k]);
+        const Request &r = s->reqs[ids[k]];
+        out[3 * k] = r.arrival_ns;
+        out[3 * k + 1] = r.admit_ns;
+        out[3 * k + 2] = r.lane == kNoRequest && !r.released ? 0 : r.done_ns;
     }
     return ok();
 }

@@ -23,7 +23,8 @@ EXPORTED = [
     "mickey_batch_set_params", "mickey_batch_get_params", "mickey_batch_autotune", "mickey_batch_free",
     "mickey_server_create", "mickey_server_submit", "mickey_server_step", "mickey_server_poll",
     "mickey_server_result", "mickey_server_copy", "mickey_server_release", "mickey_server_stats",
-    "mickey_server_state", "mickey_server_stream", "mickey_server_free",
+    "mickey_server_state", "mickey_server_stream", "mickey_server_free", "mickey_server_submit_many",
+    "mickey_server_release_many", "mickey_server_times_many", "mickey_server_wait",
 ]
 
 _lib = None
@@ -117,6 +118,14 @@ def load_library():
     L.mickey_server_stream.restype = vp
     L.mickey_server_free.argtypes = [vp]
     L.mickey_server_free.restype = None
+    L.mickey_server_submit_many.argtypes = [vp, vp, vp, sz, vp]
+    L.mickey_server_submit_many.restype = i
+    L.mickey_server_release_many.argtypes = [vp, vp, sz]
+    L.mickey_server_release_many.restype = i
+    L.mickey_server_times_many.argtypes = [vp, vp, sz, vp]
+    L.mickey_server_times_many.restype = i
+    L.mickey_server_wait.argtypes = [vp]
+    L.mickey_server_wait.restype = i
     _lib = L
     return L
 
@@ -343,15 +352,41 @@ class Server:
             _check(int(r))
         return int(r)
 
+    def submit_many(self, sids, nbits):
+        import numpy as np
+        s = np.ascontiguousarray(sids, dtype=np.uint32)
+        b = np.ascontiguousarray(nbits, dtype=np.uint64)
+        ids = np.zeros(len(s), dtype=np.int64)
+        _check(load_library().mickey_server_submit_many(self._h, s.ctypes.data, b.ctypes.data, len(s),
+                                                        ids.ctypes.data))
+        return ids
+
+    def release_many(self, ids) -> None:
+        import numpy as np
+        a = np.ascontiguousarray(ids, dtype=np.uint64)
+        _check(load_library().mickey_server_release_many(self._h, a.ctypes.data, len(a)))
+
+    def times_many(self, ids):
+        import numpy as np
+        a = np.ascontiguousarray(ids, dtype=np.uint64)
+        out = np.zeros((len(a), 3), dtype=np.uint64)
+        _check(load_library().mickey_server_times_many(self._h, a.ctypes.data, len(a), out.ctypes.data))
+        return out
+
     def step(self) -> None:
         _check(load_library().mickey_server_step(self._h))
 
-    def poll(self, cap: int = 1 << 16):
-        buf = (ctypes.c_uint64 * cap)()
-        k = load_library().mickey_server_poll(self._h, buf, cap)
+    def wait(self) -> None:
+        _check(load_library().mickey_server_wait(self._h))
+
+    def poll(self, cap: int = 1 << 20):
+        """Ids of completed requests since the last poll (numpy uint64 array)."""
+        import numpy as np
+        buf = np.empty(cap, dtype=np.uint64)
+        k = load_library().mickey_server_poll(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), cap)
         if k < 0:
             _check(int(k))
-        return [int(buf[j]) for j in range(k)]
+        return buf[:k].copy()
 
     def times(self, rid: int):
         """(arrival, admission, completion) in ns of the steady clock; raises MickeyError

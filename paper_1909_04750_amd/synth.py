@@ -83,6 +83,30 @@ def batch_requests(seed: int, n: int, max_log2: float = 24.0, min_log2: float = 
     return keys, ivs, ivb, nbits
 
 
+def serve_requests(seed: int, nstates: int, rate: float, duration: float, min_bytes: int = 4096,
+                   max_bytes: int = 64 << 20):
+    """Poisson arrivals for the served workload: (arrival_s, state_ids, nbits).
+
+    Inter-arrival gaps -ln(1-u)/rate with u = (draw(3k) >> 11) * 2^-53; state id of
+    arrival k = draw(3k+1) mod nstates (uniform); size = 4 * floor(2^(log2 min + (log2 max
+    - log2 min) * u') / 4) bytes with u' from draw(3k+2), i.e. log-uniform between
+    min_bytes and max_bytes, in whole 4-byte words; nbits = 8 * size.  Arrivals are
+    generated until `duration` seconds.  Draws use stream `seed`.
+    """
+    n_est = int(rate * duration * 1.2 + 64)
+    k = np.arange(3 * n_est, dtype=np.uint64)
+    d = draws(seed, k).reshape(n_est, 3)
+    u = (d[:, 0] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    t = np.cumsum(-np.log1p(-u) / rate)
+    n = int(np.searchsorted(t, duration))
+    t = t[:n]
+    sid = (d[:n, 1] % np.uint64(nstates)).astype(np.uint32)
+    u2 = (d[:n, 2] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    lo, hi = np.log2(min_bytes), np.log2(max_bytes)
+    size = 4 * np.floor(2.0 ** (lo + (hi - lo) * u2) / 4)
+    return t, sid, (8 * size).astype(np.uint64)
+
+
 def workload(name: str):
     """Named workloads: (seed, n instances, keystream bits per instance, IV-length recipe)."""
     table = {

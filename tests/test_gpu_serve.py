@@ -33,8 +33,8 @@ def drain(srv, max_steps=100000):
         if st["waiting"] == 0 and st["running"] == 0:
             break
         srv.step()
-        done += srv.poll()
-    done += srv.poll()
+        done += srv.poll().tolist()
+    done += srv.poll().tolist()
     return done
 
 
@@ -113,7 +113,7 @@ def test_budget_admission_and_overlap():
     # requests arriving while others run are admitted as budget frees up
     for _ in range(2000):
         srv.step()
-        for rid in srv.poll():
+        for rid in srv.poll().tolist():
             srv.release(rid)
         st = srv.stats()
         if st["running"] + st["waiting"] == 0:
