@@ -225,8 +225,9 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, rate: flo
     sat_bits = 8 * sat_bytes
     srv = mickey.Server(init, nslices=(nstates + 31) // 32, quantum_clocks=8192, budget_bytes=budget)
     all_s = np.arange(nstates, dtype=np.uint32)
-    sid_of = list(all_s)
-    srv.submit_many(all_s, np.full(nstates, sat_bits, dtype=np.uint64))
+    sid_of = np.zeros(1 << 25, dtype=np.uint32)  # request id -> state id
+    ids0 = srv.submit_many(all_s, np.full(nstates, sat_bits, dtype=np.uint64))
+    sid_of[ids0] = all_s
     t_start = time.monotonic_ns()
     b0 = None
     while True:
@@ -234,9 +235,11 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, rate: flo
         ids = srv.poll()
         if len(ids):
             srv.release_many(ids)
-            again = np.asarray([sid_of[j] for j in ids.tolist()], dtype=np.uint32)
-            sid_of.extend(again.tolist())
-            srv.submit_many(again, np.full(len(again), sat_bits, dtype=np.uint64))
+            again = sid_of[ids]
+            new = srv.submit_many(again, np.full(len(again), sat_bits, dtype=np.uint64))
+            if new.max() >= len(sid_of):
+                sid_of = np.concatenate([sid_of, np.zeros_like(sid_of)])
+            sid_of[new] = again
         el = (time.monotonic_ns() - t_start) * 1e-9
         if b0 is None and el > 1.0:  # warm-up second
             b0, tb0 = srv.stats()["bits_delivered"], time.monotonic_ns()
@@ -265,7 +268,11 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, rate: flo
                         sat_bytes >> 10, (nstates + 31) // 32, sat_seconds),
         "served_gbit_s": round(served, 3), "plain_same_instances_gbit_s": round(plain, 3),
         "served_over_plain": round(served / plain, 4), "steps": st["steps"],
-        "mean_quantum_ms": round(st["quantum_ns"] / max(st["steps"], 1) / 1e6, 3),
+        "host_s": {"blocked_on_gpu": round(st["host_wait_ns"] * 1e-9, 3),
+                   "retiring": round(st["host_retire_ns"] * 1e-9, 3),
+                   "admitting": round(st["host_admit_ns"] * 1e-9, 3),
+                   "client_and_other": round((tb1 - t_start) * 1e-9 - (st["host_wait_ns"] + st["host_retire_ns"]
+                                                                          + st["host_admit_ns"]) * 1e-9, 3)},
     }
     print("# serve closed loop: %.1f Gbit/s served vs %.1f plain" % (served, plain), file=sys.stderr, flush=True)
     return out

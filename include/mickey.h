@@ -245,8 +245,9 @@ int mickey_server_copy(const mickey_server *s, uint64_t id, uint32_t *dst, uint6
 int mickey_server_release(mickey_server *s, uint64_t id);
 
 /* [0] waiting, [1] running, [2] admitted, [3] finished, [4] steps, [5] quantum time in
- * ns, [6] keystream bits delivered, [7] free budget in 32-bit words. */
-int mickey_server_stats(const mickey_server *s, uint64_t out[8]);
+ * ns (launch to retirement), [6] keystream bits delivered, [7] free budget in 32-bit
+ * words, [8] host ns blocked on quanta, [9] host ns retiring, [10] host ns admitting. */
+int mickey_server_stats(const mickey_server *s, uint64_t out[11]);
 
 /* Device pointer to resident state `state_id` (25 bytes) and its bit counter. */
 int mickey_server_state(const mickey_server *s, uint32_t state_id, const uint8_t **packed, uint64_t *bits);

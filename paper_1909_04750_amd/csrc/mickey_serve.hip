@@ -24,6 +24,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <unordered_map>
 #include <new>
 #include <vector>
 
@@ -151,17 +152,24 @@ struct Request {
     bool released = false;
 };
 
-// First-fit allocator over the output arena, in 32-bit words.
+// Output-arena allocator, in 32-bit words: released blocks go to exact-size free lists
+// (O(1) reuse by requests of the same size); other sizes are carved first-fit from an
+// ordered map of coalesced free blocks, into which the size lists are flushed when the
+// map has no fitting block.
 struct Arena {
     size_t capacity = 0;
-    std::map<size_t, size_t> free_by_off;  // offset -> length
+    size_t cached = 0;                                   // words held in the size lists
+    std::map<size_t, size_t> free_by_off;                // offset -> length, coalesced
+    std::unordered_map<size_t, std::vector<size_t>> by_size;  // length -> offsets
     void reset(size_t words)
     {
         capacity = words;
+        cached = 0;
         free_by_off.clear();
+        by_size.clear();
         free_by_off[0] = words;
     }
-    bool alloc(size_t words, size_t *off)
+    bool first_fit(size_t words, size_t *off)
     {
         for (auto it = free_by_off.begin(); it != free_by_off.end(); ++it) {
             if (it->second >= words) {
@@ -174,7 +182,7 @@ struct Arena {
         }
         return false;
     }
-    void release(size_t off, size_t words)
+    void insert_coalesced(size_t off, size_t words)
     {
         auto it = free_by_off.emplace(off, words).first;
         auto nx = std::next(it);
@@ -189,6 +197,34 @@ struct Arena {
                 free_by_off.erase(it);
             }
         }
+    }
+    bool alloc(size_t words, size_t *off)
+    {
+        auto hit = by_size.find(words);
+        if (hit != by_size.end() && !hit->second.empty()) {
+            *off = hit->second.back();
+            hit->second.pop_back();
+            cached -= words;
+            return true;
+        }
+        if (first_fit(words, off)) return true;
+        if (!cached) return false;
+        for (auto &kv : by_size)
+            for (size_t o : kv.second) insert_coalesced(o, kv.first);
+        by_size.clear();
+        cached = 0;
+        return first_fit(words, off);
+    }
+    void release(size_t off, size_t words)
+    {
+        by_size[words].push_back(off);
+        cached += words;
+    }
+    size_t free_words() const
+    {
+        size_t f = cached;
+        for (auto &kv : free_by_off) f += kv.second;
+        return f;
     }
 };
 
@@ -216,11 +252,14 @@ struct mickey_server {
     Arena alloc;
     // host side
     Admit *hadm = nullptr;          // pinned
-    uint32_t *hcount = nullptr;     // pinned: completions of the in-flight quantum
-    uint32_t *hlist = nullptr;      // pinned, mapped: the kernel appends completed lanes here
+    // Two quanta can be in flight: quantum q uses completion buffer q & 1.
+    uint32_t *hcount = nullptr;     // pinned [2]: completions of each in-flight quantum
+    uint32_t *hlist = nullptr;      // pinned, mapped [2][nlanes]: completed lanes
     uint32_t *hlist_dev = nullptr;  // device view of hlist
-    bool inflight = false;
-    uint64_t launch_ns = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    uint64_t launch_ns[2] = {0, 0};
+    uint64_t next_q = 0, oldest_q = 0;  // quanta [oldest_q, next_q) are in flight
+    uint32_t pending = 0;               // admissions decided, not yet enqueued
     std::vector<uint64_t> state_bits;
     std::vector<uint8_t> state_busy;
     std::vector<uint32_t> free_lanes;
@@ -229,6 +268,7 @@ struct mickey_server {
     std::vector<uint64_t> lane_req;
     std::vector<uint64_t> completed;  // not yet reported
     uint64_t steps = 0, quanta_ns = 0, admitted = 0, finished = 0, bits_done = 0;
+    uint64_t ns_wait = 0, ns_retire = 0, ns_admit = 0;  // host time spent in each part
 };
 
 namespace {
@@ -243,6 +283,8 @@ void destroy(mickey_server *s)
     if (s->hadm) (void)hipHostFree(s->hadm);
     if (s->hcount) (void)hipHostFree(s->hcount);
     if (s->hlist) (void)hipHostFree(s->hlist);
+    for (hipEvent_t e : s->ev)
+        if (e) (void)hipEventDestroy(e);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -253,18 +295,22 @@ __global__ void reset_count_kernel(uint32_t *c)
     if (threadIdx.x == 0) *c = 0u;
 }
 
-// Wait for the in-flight quantum (if any) and retire the requests it completed.
-int retire(mickey_server *s)
+// Wait for the oldest in-flight quantum and retire the requests it completed.
+int retire_oldest(mickey_server *s)
 {
-    if (!s->inflight) return MICKEY_OK;
-    hipError_t e = hipStreamSynchronize(s->stream);
-    s->inflight = false;
+    if (s->oldest_q == s->next_q) return MICKEY_OK;
+    const int b = (int)(s->oldest_q & 1);
+    const uint64_t tw = now_ns();
+    hipError_t e = hipEventSynchronize(s->ev[b]);
+    s->oldest_q++;
     if (e != hipSuccess) return fail(MICKEY_EDEVICE, "quantum: %s", hipGetErrorString(e));
     const uint64_t t1 = now_ns();
-    s->quanta_ns += t1 - s->launch_ns;
-    const uint32_t ndone = *s->hcount;
+    s->ns_wait += t1 - tw;
+    s->quanta_ns += t1 - s->launch_ns[b];
+    const uint32_t ndone = s->hcount[b];
+    const uint32_t *list = s->hlist + (size_t)b * s->nlanes;
     for (uint32_t k = 0; k < ndone; k++) {
-        const uint32_t lane = s->hlist[k];
+        const uint32_t lane = list[k];
         Request &r = s->reqs[s->lane_req[lane]];
         r.done = true;
         r.done_ns = t1;
@@ -276,7 +322,48 @@ int retire(mickey_server *s)
         s->finished++;
         s->bits_done += r.nbits;
     }
+    s->ns_retire += now_ns() - t1;
     return MICKEY_OK;
+}
+
+// Decide admissions in arrival order into s->hadm (enqueued by the next step); requests
+// on busy states keep their place.
+void decide_admissions(mickey_server *s)
+{
+    const uint64_t t_admit = now_ns();
+    std::deque<uint64_t> keep;
+    bool full = false;
+    for (uint64_t id : s->waiting) {
+        Request &r = s->reqs[id];
+        if (full || s->state_busy[r.sid]) {
+            keep.push_back(id);
+            continue;
+        }
+        if (s->state_bits[r.sid] + r.nbits > MICKEY_MAX_BITS_PER_IV) {  // 2^40 per key/IV pair
+            r.done = true;
+            r.done_ns = t_admit;
+            r.lane = kNoRequest;
+            s->completed.push_back(r.id);
+            continue;
+        }
+        size_t off = 0;
+        if (s->free_lanes.empty() || !s->alloc.alloc(r.nbits / 32, &off)) {  // slots or budget full
+            full = true;
+            keep.push_back(id);
+            continue;
+        }
+        const uint32_t lane = s->free_lanes.back();
+        s->free_lanes.pop_back();
+        r.lane = lane;
+        r.out_off = off;
+        r.admit_ns = t_admit;
+        s->state_busy[r.sid] = 1;
+        s->lane_req[lane] = r.id;
+        s->hadm[s->pending++] = Admit{lane, r.sid, (uint32_t)(r.nbits / 32), 0u, s->arena + off};
+        s->admitted++;
+    }
+    s->waiting.swap(keep);
+    s->ns_admit += now_ns() - t_admit;
 }
 
 }  // namespace
@@ -324,8 +411,10 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
                hipMalloc(&s->arena, budget_words * 4) == hipSuccess &&
                hipHostMalloc((void **)&s->hadm, s->nlanes * sizeof(Admit), hipHostMallocDefault) == hipSuccess &&
                hipHostMalloc((void **)&s->hcount, 64, hipHostMallocDefault) == hipSuccess &&
-               hipHostMalloc((void **)&s->hlist, s->nlanes * 4, hipHostMallocMapped) == hipSuccess &&
-               hipHostGetDevicePointer((void **)&s->hlist_dev, s->hlist, 0) == hipSuccess;
+               hipHostMalloc((void **)&s->hlist, 2 * s->nlanes * 4, hipHostMallocMapped) == hipSuccess &&
+               hipHostGetDevicePointer((void **)&s->hlist_dev, s->hlist, 0) == hipSuccess &&
+               hipEventCreateWithFlags(&s->ev[0], hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&s->ev[1], hipEventDisableTiming) == hipSuccess;
     if (!okm) {
         (void)hipGetLastError();
         destroy(s);
@@ -333,7 +422,7 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
              (unsigned long long)budget_bytes);
         return nullptr;
     }
-    s->done_count = s->done_list;  // device word: completions of the in-flight quantum
+    s->done_count = s->done_list;  // device words [2]: completions of each in-flight quantum
     // the initial states: the registers of the given initialised instances
     int rc = mickey_state_export(init, s->pool, nullptr);
     if (rc == MICKEY_OK && (hipMemsetAsync(s->lane_left, 0, s->nlanes * 4) != hipSuccess ||
@@ -375,75 +464,55 @@ int64_t mickey_server_submit(mickey_server *s, uint32_t state_id, uint64_t nbits
 int mickey_server_step(mickey_server *s)
 {
     if (!s) return fail(MICKEY_EINVAL, "mickey_server_step: NULL server");
-    // 1. retire what the previous quantum completed
-    int rc = retire(s);
-    if (rc != MICKEY_OK) return rc;
-    // 2. admit in arrival order; requests on busy states keep their place
-    uint32_t nadm = 0;
-    const uint64_t t_admit = now_ns();
-    std::deque<uint64_t> keep;
-    bool full = false;
-    for (uint64_t id : s->waiting) {
-        Request &r = s->reqs[id];
-        if (full || s->state_busy[r.sid]) {
-            keep.push_back(id);
-            continue;
-        }
-        if (s->state_bits[r.sid] + r.nbits > MICKEY_MAX_BITS_PER_IV) {  // 2^40 per key/IV pair
-            r.done = true;
-            r.done_ns = t_admit;
-            r.lane = kNoRequest;
-            s->completed.push_back(r.id);
-            continue;
-        }
-        size_t off = 0;
-        if (s->free_lanes.empty() || !s->alloc.alloc(r.nbits / 32, &off)) {  // slots or budget full
-            full = true;
-            keep.push_back(id);
-            continue;
-        }
-        const uint32_t lane = s->free_lanes.back();
-        s->free_lanes.pop_back();
-        r.lane = lane;
-        r.out_off = off;
-        r.admit_ns = t_admit;
-        s->state_busy[r.sid] = 1;
-        s->lane_req[lane] = r.id;
-        s->hadm[nadm++] = Admit{lane, r.sid, (uint32_t)(r.nbits / 32), 0u, s->arena + off};
-        s->admitted++;
-    }
-    s->waiting.swap(keep);
-    // 3. gather
-    if (nadm) {
-        if (hipMemcpyAsync(s->dadm, s->hadm, nadm * sizeof(Admit), hipMemcpyHostToDevice, s->stream) != hipSuccess)
+    int rc = MICKEY_OK;
+    if (s->oldest_q == s->next_q) decide_admissions(s);  // idle: admit before launching
+    // 1. gather the admissions decided last time (stream-ordered after the quanta in flight)
+    if (s->pending) {
+        if (hipMemcpyAsync(s->dadm, s->hadm, s->pending * sizeof(Admit), hipMemcpyHostToDevice, s->stream) !=
+            hipSuccess)
             return check_launch("admission upload");
-        hipLaunchKernelGGL(admit_kernel, dim3((nadm + 255) / 256), dim3(256), 0, s->stream, s->dadm, nadm, s->pool,
-                           s->planes, (uint32_t)s->nslices, s->lane_out, s->lane_left, s->lane_sid);
+        hipLaunchKernelGGL(admit_kernel, dim3((s->pending + 255) / 256), dim3(256), 0, s->stream, s->dadm,
+                           s->pending, s->pool, s->planes, (uint32_t)s->nslices, s->lane_out, s->lane_left,
+                           s->lane_sid);
         rc = check_launch("admit_kernel");
         if (rc != MICKEY_OK) return rc;
+        s->pending = 0;
     }
-    if (s->free_lanes.size() == s->nlanes) return ok();  // nothing to run
-    // 4. one quantum; the host learns its completions at the next step
-    hipLaunchKernelGGL(reset_count_kernel, dim3(1), dim3(64), 0, s->stream, s->done_count);
-    s->launch_ns = now_ns();
-    hipLaunchKernelGGL(quantum_kernel, dim3((unsigned)(s->nslices / 64)), dim3(64), 0, s->stream, s->planes,
-                       (uint32_t)s->nslices, s->qblocks, s->lane_out, s->lane_left, s->lane_sid, s->pool,
-                       s->hlist_dev, s->done_count);
-    rc = check_launch("quantum_kernel");
-    if (rc != MICKEY_OK) return rc;
-    if (hipMemcpyAsync(s->hcount, s->done_count, 4, hipMemcpyDeviceToHost, s->stream) != hipSuccess)
-        return check_launch("completion count");
-    s->inflight = true;
-    s->steps++;
+    // 2. launch the next quantum when any lane is occupied
+    if (s->free_lanes.size() < s->nlanes) {
+        const int b = (int)(s->next_q & 1);
+        hipLaunchKernelGGL(reset_count_kernel, dim3(1), dim3(64), 0, s->stream, s->done_count + b);
+        s->launch_ns[b] = now_ns();
+        hipLaunchKernelGGL(quantum_kernel, dim3((unsigned)(s->nslices / 64)), dim3(64), 0, s->stream, s->planes,
+                           (uint32_t)s->nslices, s->qblocks, s->lane_out, s->lane_left, s->lane_sid, s->pool,
+                           s->hlist_dev + (size_t)b * s->nlanes, s->done_count + b);
+        rc = check_launch("quantum_kernel");
+        if (rc != MICKEY_OK) return rc;
+        if (hipMemcpyAsync(s->hcount + b, s->done_count + b, 4, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+            hipEventRecord(s->ev[b], s->stream) != hipSuccess)
+            return check_launch("completion count");
+        s->next_q++;
+        s->steps++;
+    }
+    // 3. retire the previous quantum while this one runs (or the last one, if idle), then
+    //    decide what the lanes it freed take next
+    if (s->next_q - s->oldest_q >= 2 || (s->next_q > s->oldest_q && s->free_lanes.size() == s->nlanes)) {
+        rc = retire_oldest(s);
+        if (rc != MICKEY_OK) return rc;
+    }
+    decide_admissions(s);
     return ok();
 }
 
-// Wait for the in-flight quantum and retire its requests (no new work is started).
+// Wait for every quantum in flight and retire its requests (no new work is started).
 int mickey_server_wait(mickey_server *s)
 {
     if (!s) return fail(MICKEY_EINVAL, "mickey_server_wait: NULL server");
-    int rc = retire(s);
-    return rc == MICKEY_OK ? ok() : rc;
+    while (s->oldest_q != s->next_q) {
+        int rc = retire_oldest(s);
+        if (rc != MICKEY_OK) return rc;
+    }
+    return ok();
 }
 
 // Many submissions at once: ids[k] receives the id of (sids[k], nbits[k]), or a negative
@@ -531,12 +600,13 @@ int mickey_server_release(mickey_server *s, uint64_t id)
 }
 
 // Counters: [0] waiting, [1] running, [2] admitted, [3] finished, [4] steps,
-// [5] total quantum time (ns), [6] keystream bits delivered, [7] free budget words.
-int mickey_server_stats(const mickey_server *s, uint64_t out[8])
+// [5] total quantum time (ns, launch to retirement), [6] keystream bits delivered,
+// [7] free budget words, [8] host ns blocked on quanta, [9] host ns retiring,
+// [10] host ns deciding admissions.
+int mickey_server_stats(const mickey_server *s, uint64_t out[11])
 {
     if (!s || !out) return fail(MICKEY_EINVAL, "mickey_server_stats: bad argument");
-    size_t freew = 0;
-    for (auto &kv : s->alloc.free_by_off) freew += kv.second;
+    const size_t freew = s->alloc.free_words();
     out[0] = s->waiting.size();
     out[1] = s->nlanes - s->free_lanes.size();
     out[2] = s->admitted;
@@ -545,6 +615,9 @@ int mickey_server_stats(const mickey_server *s, uint64_t out[8])
     out[5] = s->quanta_ns;
     out[6] = s->bits_done;
     out[7] = freew;
+    out[8] = s->ns_wait;
+    out[9] = s->ns_retire;
+    out[10] = s->ns_admit;
     return ok();
 }
 
