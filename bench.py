@@ -123,16 +123,23 @@ def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 
         tune = json.load(open(os.path.join(td, "batch_tune.json")))
     bs = torch.cuda.ExternalStream(b.stream_handle)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(bs)
-    b.run()
-    e1.record(bs)
-    b.sync()
-    batch_ms = e0.elapsed_time(e1)
+
+    def timed_run():
+        torch.cuda.synchronize()
+        e0.record(bs)
+        b.run()
+        e1.record(bs)
+        b.sync()
+        return e0.elapsed_time(e1)
+    batch_ms = timed_run()  # size-aware routing (automatic threshold)
+    routing = b.routing()
+    b.set_latency_threshold(mickey.Batch.LATENCY_OFF)
+    bs_only_ms = timed_run()  # every request bitsliced
     b.close()
     del arena
     total_bits = int(nbits.sum())
-    print("# batch-10k: %.1f ms (params %s)" % (batch_ms, params), file=sys.stderr, flush=True)
+    print("# batch-10k: %.1f ms routed (%s), %.1f ms all bitsliced (params %s)" % (batch_ms, routing, bs_only_ms, params),
+          file=sys.stderr, flush=True)
     # per-request plain launches (mickey_init with n = 1, then row-major generate) on a
     # sample of requests up to 2^16 bits, fitted as a + b * nbits
     stream = torch.cuda.current_stream()
@@ -161,16 +168,22 @@ def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 
             "gbit_s": round(total_bits / (batch_ms * 1e-3) / 1e9, 3),
             "params": {"unroll": params[0], "waves_per_block": params[1], "word_bits": 32,
                        "tune_timings_ms": tune.get("timings_ms")},
-            "critical_path": {"longest_bits": lmax, "bound_ms": round(bound_ms, 2),
-                              "batch_over_bound": round(batch_ms / bound_ms, 4),
-                              "clock_ns_single_lane": round(slope * 1e6, 2)},
+            "routing": {"latency_threshold_bits": routing[0], "latency_requests": routing[1],
+                        "latency_clock_ratio": round(routing[2], 4),
+                        "bitsliced_only_ms": round(bs_only_ms, 2)},
+            "critical_path": {"longest_bits": lmax,
+                              "bitsliced_bound_ms": round(bound_ms, 2),
+                              "bitsliced_only_over_bound": round(bs_only_ms / bound_ms, 4),
+                              "latency_mode_bound_ms": round(bound_ms * routing[2], 2),
+                              "batch_over_latency_bound": round(batch_ms / (bound_ms * routing[2]), 4),
+                              "clock_ns_single_bitsliced_lane": round(slope * 1e6, 2)},
             "per_request_plain": {"sampled": len(ts), "fit_ms": [round(icpt, 4), round(slope * 1e6, 4)],
                                   "fit_units": ["ms", "ns per bit"], "extrapolated_serial_ms": round(serial_ms, 1),
                                   "batch_speedup": round(serial_ms / batch_ms, 1)}}
 
 
 def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, rate: float = 20000.0,
-                nstates: int = 10 ** 6, budget: int = 64 << 30, sat_bytes: int = 32 << 10, sat_seconds: float = 3.0):
+                nstates: int = 10 ** 6, budget: int = 64 << 30, sat_bytes: int = 56 << 10, sat_seconds: float = 3.0):
     """Served generation over 10^6 resident states (splitmix64 seed 5 keys and 80-bit
     IVs, initialised).  Open loop: Poisson arrivals at `rate`/s for `duration` s, state
     uniform, size log-uniform in [4 KiB, max_bytes]; latency = completion - scheduled
@@ -223,10 +236,14 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, rate: flo
           out["open_loop"]["latency_s"]["p99"]), file=sys.stderr, flush=True)
     # -- closed loop: every state busy
     sat_bits = 8 * sat_bytes
+    srng = np.random.default_rng(55)
+
+    def sizes(k):  # bits, whole 32-bit words, uniform in sat_bytes +- 8 KiB
+        return (8 * 4 * srng.integers((sat_bytes - (8 << 10)) // 4, (sat_bytes + (8 << 10)) // 4 + 1, k)).astype(np.uint64)
     srv = mickey.Server(init, nslices=(nstates + 31) // 32, quantum_clocks=8192, budget_bytes=budget)
     all_s = np.arange(nstates, dtype=np.uint32)
     sid_of = np.zeros(1 << 25, dtype=np.uint32)  # request id -> state id
-    ids0 = srv.submit_many(all_s, np.full(nstates, sat_bits, dtype=np.uint64))
+    ids0 = srv.submit_many(all_s, sizes(nstates))
     sid_of[ids0] = all_s
     t_start = time.monotonic_ns()
     b0 = None
@@ -236,7 +253,7 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, rate: flo
         if len(ids):
             srv.release_many(ids)
             again = sid_of[ids]
-            new = srv.submit_many(again, np.full(len(again), sat_bits, dtype=np.uint64))
+            new = srv.submit_many(again, sizes(len(again)))
             if new.max() >= len(sid_of):
                 sid_of = np.concatenate([sid_of, np.zeros_like(sid_of)])
             sid_of[new] = again
@@ -263,8 +280,8 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, rate: flo
     del buf
     init.close()
     out["closed_loop"] = {
-        "workload": "every one of the 10^6 states keeps one %d KiB request in flight (resubmitted on completion), "
-                    "%d slots, quantum 8192 clocks, measured over %.1f s after 1 s warm-up" % (
+        "workload": "every one of the 10^6 states keeps one request of %d+-8 KiB in flight (resubmitted on "
+                    "completion), %d slots, quantum 8192 clocks, measured over %.1f s after 1 s warm-up" % (
                         sat_bytes >> 10, (nstates + 31) // 32, sat_seconds),
         "served_gbit_s": round(served, 3), "plain_same_instances_gbit_s": round(plain, 3),
         "served_over_plain": round(served / plain, 4), "steps": st["steps"],

@@ -175,11 +175,25 @@ int mickey_batch_set_params(mickey_batch *b, int unroll, int waves_per_block);
 int mickey_batch_get_params(const mickey_batch *b, int *unroll, int *waves_per_block);
 
 /* Autotuner: times every built variant on the current requests with lengths capped at
- * cap_bits (a multiple of 32; outputs go to scratch memory), keeps the fastest and
+ * cap_bits (a multiple of 32; outputs go to scratch memory), keeps the fastest, times
+ * the same capped requests in latency mode to set the routing ratio r, and
  * re-captures.  With cache_path, a JSON record of the choice is read from that file
  * when its signature (architecture, request count, capped lengths) matches, and written
  * there otherwise.  Synchronises the batch's stream. */
 int mickey_batch_autotune(mickey_batch *b, uint64_t cap_bits, const char *cache_path);
+
+/* Size-aware routing: requests of at least `bits` bits run in latency mode (one
+ * request per lane with a word-parallel clock: ~5x more VALU work per bit, but a lone
+ * instance advances ~6x faster), the rest bitsliced; both run concurrently in the same
+ * graph and give identical words.  0 (the default) sets the threshold automatically
+ * to L_max * r, r being the tuned ratio of the two engines' clock times, so that the
+ * bitsliced part finishes before the longest request; UINT64_MAX turns latency mode
+ * off.  At most 65536 requests take latency mode. */
+int mickey_batch_set_latency_threshold(mickey_batch *b, uint64_t bits);
+/* The threshold in use (UINT64_MAX if none), how many requests take latency mode, and
+ * the clock-time ratio r. */
+int mickey_batch_get_routing(const mickey_batch *b, uint64_t *threshold, size_t *latency_requests,
+                             double *latency_clock_ratio);
 
 void mickey_batch_free(mickey_batch *b);
 

@@ -10,6 +10,7 @@
 // lane stops storing when its own words are done.
 #include "mickey_device.h"
 #include "mickey_host.h"
+#include "mickey_wordpar.h"
 
 #include <hip/hip_runtime.h>
 
@@ -73,6 +74,68 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     }
 }
 
+// Latency mode: one request per lane, word-parallel clock.  Lane i runs request
+// order[i]: the same input string as the bitsliced staging (IV right-aligned to clock
+// 80, then the key, then 100 zero clocks), lanes with IV length L idle for 80 - L
+// clocks, then 32 clocks per output word (first bit in the MSB).
+__global__ __launch_bounds__(64) void latency_kernel(const uint8_t *__restrict__ keys, const uint8_t *__restrict__ ivs,
+                                                     const uint8_t *__restrict__ iv_bits,
+                                                     const uint32_t *__restrict__ order, uint32_t nlanes,
+                                                     uint32_t *const *__restrict__ lane_out,
+                                                     const uint32_t *__restrict__ lane_words)
+{
+    const uint32_t i = blockIdx.x * 64u + threadIdx.x;
+    if (i >= nlanes) return;
+    const uint32_t req = order[i];
+    const uint8_t *k = keys + 10ull * req;
+    const uint8_t *v = ivs + 10ull * req;
+    uint64_t kh = 0, ih = 0;
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+        kh = (kh << 8) | k[b];
+        ih = (ih << 8) | v[b];
+    }
+    const uint32_t kl = ((uint32_t)k[8] << 8) | k[9], il = ((uint32_t)v[8] << 8) | v[9];
+    uint32_t L = iv_bits ? iv_bits[req] : 80u;
+    if (L > 80u) L = 80u;  // lengths are validated on the host before any run
+    typedef unsigned __int128 u128;
+    const u128 key80 = ((u128)kh << 16) | kl, iv80 = ((u128)ih << 16) | il;
+    const u128 ivL = L ? (iv80 >> (80u - L)) : (u128)0;
+    const u128 lo = key80 | (ivL << 80);
+    const uint32_t w[5] = {(uint32_t)(ivL >> 48), (uint32_t)(lo >> 96), (uint32_t)(lo >> 64), (uint32_t)(lo >> 32),
+                           (uint32_t)lo};
+    const uint32_t d = 80u - L;
+    WState x;
+#pragma unroll
+    for (int q = 0; q < 4; q++) x.r[q] = x.s[q] = 0u;
+#pragma unroll
+    for (int c = 0; c < 5; c++) {  // the 160 input clocks, 32 per input word
+        for (uint32_t b = 0; b < 32u; b += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const uint32_t t = 32u * c + b + u;
+                const uint32_t in_m = (uint32_t)((int32_t)(w[c] << (b + u)) >> 31);
+                if (t >= d) wclock<true>(x, in_m);  // lanes with short IVs start late
+            }
+        }
+    }
+    for (uint32_t t = 0; t < 100u; t += 4) {  // preclocks
+#pragma unroll
+        for (int u = 0; u < 4; u++) wclock<true>(x, 0u);
+    }
+    uint32_t *out = lane_out[i];
+    const uint32_t nw = lane_words[i];
+    for (uint32_t j = 0; j < nw; j++) {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int b = 0; b < 32; b++) {
+            acc = __builtin_amdgcn_alignbit(x.r[0] ^ x.s[0], acc, 1);  // z enters at bit 31
+            wclock<false>(x, 0u);
+        }
+        out[j] = __builtin_bitreverse32(acc);  // first bit of the word in the MSB
+    }
+}
+
 typedef void (*BatchKernelFn)(const uint32_t *, const uint32_t *, uint32_t, uint32_t, uint32_t, const uint32_t *,
                               uint32_t *const *, const uint32_t *, uint32_t *);
 
@@ -109,31 +172,41 @@ int resident_waves()
 struct mickey_batch {
     size_t max_req = 0;
     size_t max_groups_pad = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // the batch's stream (bitsliced branch)
+    hipStream_t side = nullptr;    // latency branch of the graph
     bool own_stream = false;
+    hipEvent_t fork = nullptr, join = nullptr;
     // device buffers (one allocation)
     void *dmem = nullptr;
-    uint32_t *order = nullptr;       // [slots] request of each slot, kNoRequest for padding
-    uint32_t **lane_out = nullptr;   // [slots]
-    uint32_t *lane_words = nullptr;  // [slots]
-    uint32_t *group_words = nullptr; // [groups]
-    uint32_t *counter = nullptr;     // work queue head
-    uint32_t *status = nullptr;      // IV length check
-    uint32_t *in_planes = nullptr;   // [160][groups_pad]
-    uint32_t *mask_planes = nullptr; // [96][groups_pad]
-    uint32_t *host_status = nullptr; // pinned
-    // current requests
+    uint32_t *order = nullptr;        // [slots] request of each bitsliced slot, kNoRequest for padding
+    uint32_t **lane_out = nullptr;    // [slots]
+    uint32_t *lane_words = nullptr;   // [slots]
+    uint32_t *group_words = nullptr;  // [groups]
+    uint32_t *counter = nullptr;      // work queue head
+    uint32_t *status = nullptr;       // IV length check
+    uint32_t *in_planes = nullptr;    // [160][groups_pad]
+    uint32_t *mask_planes = nullptr;  // [96][groups_pad]
+    uint32_t *lat_order = nullptr;    // [max_req] request of each latency lane
+    uint32_t **lat_out = nullptr;     // [max_req]
+    uint32_t *lat_words = nullptr;    // [max_req]
+    uint32_t *host_status = nullptr;  // pinned
+    // current requests and their routing
     const uint8_t *keys = nullptr, *ivs = nullptr, *iv_bits = nullptr;
-    size_t nreq = 0, ngroups = 0, groups_pad = 0, ntasks = 0;
+    size_t nreq = 0, ngroups = 0, groups_pad = 0, ntasks = 0, nlat = 0;
     std::vector<uint64_t> nbits;
     std::vector<uint32_t *> outs;
-    std::vector<uint32_t> host_order;
+    std::vector<uint32_t> host_order, lat_host_order;
     int unroll = 4, wpb = 1;
+    uint64_t lat_setting = 0;  // 0: automatic threshold, ~0: latency mode off, else threshold in bits
+    double lat_ratio = 0.16;   // latency-lane clock time / bitsliced-slice clock time (tuned)
+    uint64_t lat_threshold = ~0ull;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
 
 namespace {
+
+constexpr size_t kMaxLatencyLanes = 65536;  // 1024 waves of word-parallel lanes
 
 void drop_graph(mickey_batch *b)
 {
@@ -143,9 +216,79 @@ void drop_graph(mickey_batch *b)
     b->graph = nullptr;
 }
 
-// Enqueue the batch on b->stream: reset the queue head, stage the inputs of every slot,
-// launch the persistent kernel.
-int enqueue(mickey_batch *b, const Variant &v)
+// Size-aware routing: requests of at least `threshold` bits run in latency mode (one
+// lane each, word-parallel clock), the others bitsliced (32 per slice), each part
+// sorted longest first.  The automatic threshold is L_max * (latency-lane clock /
+// bitsliced clock): shorter requests finish in bitsliced mode before the longest
+// request finishes in latency mode.  At most kMaxLatencyLanes requests take latency mode.
+void route(mickey_batch *b, const std::vector<uint64_t> &nbits, uint64_t setting)
+{
+    const size_t n = nbits.size();
+    uint64_t lmax = 0;
+    for (uint64_t v : nbits) lmax = std::max(lmax, v);
+    uint64_t th = ~0ull;
+    if (setting == 0) {
+        const uint64_t auto_th = (uint64_t)((double)lmax * b->lat_ratio);
+        th = std::max<uint64_t>(auto_th, 1u << 12);
+    } else if (setting != ~0ull) {
+        th = setting;
+    }
+    std::vector<uint32_t> idx(n);
+    std::iota(idx.begin(), idx.end(), 0u);
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t c) { return nbits[a] > nbits[c]; });
+    size_t nl = 0;
+    while (nl < n && nbits[idx[nl]] >= th && nbits[idx[nl]] > 0 && nl < kMaxLatencyLanes) nl++;
+    if (nl < n && nl == kMaxLatencyLanes) th = nbits[idx[nl - 1]];
+    b->lat_threshold = nl ? th : ~0ull;
+    b->nlat = nl;
+    b->lat_host_order.assign(idx.begin(), idx.begin() + nl);
+    const size_t nshort = n - nl;
+    b->ngroups = (nshort + 31) / 32;
+    b->groups_pad = (b->ngroups + 63) / 64 * 64;
+    b->ntasks = b->groups_pad / 64;
+    b->host_order.assign(b->groups_pad * 32, kNoRequest);
+    std::copy(idx.begin() + nl, idx.end(), b->host_order.begin());
+}
+
+// Upload both parts' metadata for the given lengths and outputs (routing unchanged).
+int upload_meta(mickey_batch *b, const std::vector<uint64_t> &nbits, const std::vector<uint32_t *> &outs)
+{
+    const size_t nslots = b->groups_pad * 32;
+    std::vector<uint32_t> words(nslots, 0u), gwords(b->groups_pad, 0u), lwords(b->nlat);
+    std::vector<uint32_t *> lo(nslots, nullptr), llo(b->nlat);
+    for (size_t s = 0; s < nslots; s++) {
+        const uint32_t r = b->host_order[s];
+        if (r == kNoRequest) continue;
+        words[s] = (uint32_t)(nbits[r] / 32);
+        lo[s] = outs[r];
+        gwords[s / 32] = std::max(gwords[s / 32], words[s]);
+    }
+    for (size_t i = 0; i < b->nlat; i++) {
+        lwords[i] = (uint32_t)(nbits[b->lat_host_order[i]] / 32);
+        llo[i] = outs[b->lat_host_order[i]];
+    }
+    bool okc = true;
+    if (nslots)
+        okc = hipMemcpyAsync(b->order, b->host_order.data(), nslots * 4, hipMemcpyHostToDevice, b->stream) ==
+                  hipSuccess &&
+              hipMemcpyAsync(b->lane_words, words.data(), nslots * 4, hipMemcpyHostToDevice, b->stream) ==
+                  hipSuccess &&
+              hipMemcpyAsync(b->lane_out, lo.data(), nslots * sizeof(uint32_t *), hipMemcpyHostToDevice,
+                             b->stream) == hipSuccess &&
+              hipMemcpyAsync(b->group_words, gwords.data(), b->groups_pad * 4, hipMemcpyHostToDevice, b->stream) ==
+                  hipSuccess;
+    if (okc && b->nlat)
+        okc = hipMemcpyAsync(b->lat_order, b->lat_host_order.data(), b->nlat * 4, hipMemcpyHostToDevice,
+                             b->stream) == hipSuccess &&
+              hipMemcpyAsync(b->lat_words, lwords.data(), b->nlat * 4, hipMemcpyHostToDevice, b->stream) ==
+                  hipSuccess &&
+              hipMemcpyAsync(b->lat_out, llo.data(), b->nlat * sizeof(uint32_t *), hipMemcpyHostToDevice,
+                             b->stream) == hipSuccess;
+    if (!okc || hipStreamSynchronize(b->stream) != hipSuccess) return check_launch("batch metadata upload");
+    return MICKEY_OK;
+}
+
+int launch_bitsliced(mickey_batch *b, const Variant &v)
 {
     hipLaunchKernelGGL(reset_words_kernel, dim3(1), dim3(64), 0, b->stream, b->counter, 2u);
     int rc = check_launch("reset_words_kernel");
@@ -162,13 +305,36 @@ int enqueue(mickey_batch *b, const Variant &v)
     if (rc != MICKEY_OK) return rc;
     const int waves = (int)std::min<size_t>(b->ntasks, (size_t)resident_waves());
     const int blocks = (waves + v.wpb - 1) / v.wpb;
-    if (blocks > 0) {
-        hipLaunchKernelGGL(v.fn, dim3(blocks), dim3(64 * v.wpb), 0, b->stream, b->in_planes, b->mask_planes,
-                           (uint32_t)b->groups_pad, (uint32_t)b->ngroups, (uint32_t)b->ntasks, b->group_words,
-                           b->lane_out, b->lane_words, b->counter);
-        rc = check_launch("batch_kernel");
+    hipLaunchKernelGGL(v.fn, dim3(blocks), dim3(64 * v.wpb), 0, b->stream, b->in_planes, b->mask_planes,
+                       (uint32_t)b->groups_pad, (uint32_t)b->ngroups, (uint32_t)b->ntasks, b->group_words,
+                       b->lane_out, b->lane_words, b->counter);
+    return check_launch("batch_kernel");
+}
+
+int launch_latency(mickey_batch *b, hipStream_t s)
+{
+    hipLaunchKernelGGL(latency_kernel, dim3((unsigned)((b->nlat + 63) / 64)), dim3(64), 0, s, b->keys, b->ivs,
+                       b->iv_bits, b->lat_order, (uint32_t)b->nlat, b->lat_out, b->lat_words);
+    return check_launch("latency_kernel");
+}
+
+// Enqueue the batch on b->stream: the bitsliced part (queue reset, input staging,
+// persistent kernel) and, concurrently on the side stream, the latency part.
+int enqueue(mickey_batch *b, const Variant &v)
+{
+    int rc = MICKEY_OK;
+    if (b->nlat && b->ngroups) {
+        if (hipEventRecord(b->fork, b->stream) != hipSuccess || hipStreamWaitEvent(b->side, b->fork, 0) != hipSuccess)
+            return check_launch("fork");
+        rc = launch_latency(b, b->side);
+        if (rc == MICKEY_OK) rc = launch_bitsliced(b, v);
+        if (hipEventRecord(b->join, b->side) != hipSuccess || hipStreamWaitEvent(b->stream, b->join, 0) != hipSuccess)
+            return check_launch("join");
+        return rc;
     }
-    return rc;
+    if (b->nlat) return launch_latency(b, b->stream);
+    if (b->ngroups) return launch_bitsliced(b, v);
+    return MICKEY_OK;
 }
 
 int capture(mickey_batch *b)
@@ -195,38 +361,45 @@ int capture(mickey_batch *b)
     return MICKEY_OK;
 }
 
-// Upload slot metadata for the given lengths and output pointers (sorted order kept).
-int upload_meta(mickey_batch *b, const std::vector<uint64_t> &nbits, const std::vector<uint32_t *> &outs)
+// Route, upload and capture the current requests.
+int prepare(mickey_batch *b)
 {
-    const size_t nslots = b->groups_pad * 32;
-    std::vector<uint32_t> words(nslots, 0u), gwords(b->groups_pad, 0u);
-    std::vector<uint32_t *> lo(nslots, nullptr);
-    for (size_t s = 0; s < nslots; s++) {
-        const uint32_t r = b->host_order[s];
-        if (r == kNoRequest) continue;
-        words[s] = (uint32_t)(nbits[r] / 32);
-        lo[s] = outs[r];
-        gwords[s / 32] = std::max(gwords[s / 32], words[s]);
-    }
-    if (hipMemcpyAsync(b->lane_words, words.data(), nslots * 4, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-        hipMemcpyAsync(b->lane_out, lo.data(), nslots * sizeof(uint32_t *), hipMemcpyHostToDevice, b->stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(b->group_words, gwords.data(), b->groups_pad * 4, hipMemcpyHostToDevice, b->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(b->stream) != hipSuccess)
-        return check_launch("batch metadata upload");
-    return MICKEY_OK;
+    route(b, b->nbits, b->lat_setting);
+    int rc = upload_meta(b, b->nbits, b->outs);
+    return rc == MICKEY_OK ? capture(b) : rc;
 }
 
 void destroy(mickey_batch *b)
 {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->side) (void)hipStreamSynchronize(b->side);
     drop_graph(b);
     if (b->dmem) (void)hipFree(b->dmem);
     if (b->host_status) (void)hipHostFree(b->host_status);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
+    if (b->side) (void)hipStreamDestroy(b->side);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
+}
+
+// Time one enqueue on b->stream (ms), after one warm-up.
+int time_enqueue(mickey_batch *b, const Variant &v, hipEvent_t e0, hipEvent_t e1, float *ms)
+{
+    int rc = enqueue(b, v);
+    *ms = 1e30f;
+    for (int rep = 0; rep < 2 && rc == MICKEY_OK; rep++) {
+        (void)hipEventRecord(e0, b->stream);
+        rc = enqueue(b, v);
+        (void)hipEventRecord(e1, b->stream);
+        if (rc != MICKEY_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess) return check_launch("autotune timing");
+        float t = 0;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        *ms = std::min(*ms, t);
+    }
+    return rc;
 }
 
 }  // namespace
@@ -249,31 +422,39 @@ mickey_batch *mickey_batch_create(size_t max_requests, void *hip_stream)
     b->max_groups_pad = (groups + 63) / 64 * 64;
     if (hip_stream) {
         b->stream = (hipStream_t)hip_stream;
-    } else {
-        if (hipStreamCreate(&b->stream) != hipSuccess) {
-            delete b;
-            fail(MICKEY_EDEVICE, "mickey_batch_create: cannot create a stream");
-            return nullptr;
-        }
+    } else if (hipStreamCreate(&b->stream) == hipSuccess) {
         b->own_stream = true;
+    } else {
+        delete b;
+        fail(MICKEY_EDEVICE, "mickey_batch_create: cannot create a stream");
+        return nullptr;
     }
     const size_t slots = b->max_groups_pad * 32;
     const size_t bytes = slots * (4 + sizeof(uint32_t *) + 4) + b->max_groups_pad * 4 + 256 +
-                         (size_t)(kInputPlanes + kMaskPlanes) * b->max_groups_pad * 4;
-    if (hipMalloc(&b->dmem, bytes) != hipSuccess ||
+                         (size_t)(kInputPlanes + kMaskPlanes) * b->max_groups_pad * 4 +
+                         max_requests * (4 + sizeof(uint32_t *) + 4) + 256;
+    if (hipStreamCreate(&b->side) != hipSuccess || hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess || hipMalloc(&b->dmem, bytes) != hipSuccess ||
         hipHostMalloc((void **)&b->host_status, 4, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         destroy(b);
-        fail(MICKEY_ENOMEM, "mickey_batch_create: cannot allocate %zu bytes", bytes);
+        fail(MICKEY_ENOMEM, "mickey_batch_create: cannot allocate %zu bytes or a stream", bytes);
         return nullptr;
     }
     char *p = (char *)b->dmem;
     b->lane_out = (uint32_t **)p;
     p += slots * sizeof(uint32_t *);
+    b->lat_out = (uint32_t **)p;
+    p += max_requests * sizeof(uint32_t *);
     b->order = (uint32_t *)p;
     p += slots * 4;
     b->lane_words = (uint32_t *)p;
     p += slots * 4;
+    b->lat_order = (uint32_t *)p;
+    p += max_requests * 4;
+    b->lat_words = (uint32_t *)p;
+    p += max_requests * 4;
+    p = (char *)(((uintptr_t)p + 255) & ~(uintptr_t)255);
     b->group_words = (uint32_t *)p;
     p += b->max_groups_pad * 4;
     b->counter = (uint32_t *)p;  // counter and status share one 256-byte line
@@ -311,23 +492,9 @@ int mickey_batch_set(mickey_batch *b, const uint8_t *keys, const uint8_t *ivs, c
     b->ivs = ivs;
     b->iv_bits = iv_bits;
     b->nreq = nreq;
-    b->ngroups = (nreq + 31) / 32;
-    b->groups_pad = (b->ngroups + 63) / 64 * 64;
-    b->ntasks = b->groups_pad / 64;
     b->nbits.assign(nbits, nbits + nreq);
     b->outs.assign(outs, outs + nreq);
-    // longest first; ties keep request order
-    std::vector<uint32_t> idx(nreq);
-    std::iota(idx.begin(), idx.end(), 0u);
-    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t c) { return nbits[a] > nbits[c]; });
-    b->host_order.assign(b->groups_pad * 32, kNoRequest);
-    std::copy(idx.begin(), idx.end(), b->host_order.begin());
-    if (hipMemcpyAsync(b->order, b->host_order.data(), b->host_order.size() * 4, hipMemcpyHostToDevice,
-                       b->stream) != hipSuccess)
-        return check_launch("order upload");
-    int rc = upload_meta(b, b->nbits, b->outs);
-    if (rc != MICKEY_OK) return rc;
-    rc = capture(b);
+    int rc = prepare(b);
     return rc == MICKEY_OK ? ok() : rc;
 }
 
@@ -373,6 +540,27 @@ int mickey_batch_get_params(const mickey_batch *b, int *unroll, int *waves_per_b
     return ok();
 }
 
+int mickey_batch_set_latency_threshold(mickey_batch *b, uint64_t bits)
+{
+    if (!b) return fail(MICKEY_EINVAL, "mickey_batch_set_latency_threshold: NULL batch");
+    b->lat_setting = bits;
+    if (b->nreq) {
+        int rc = prepare(b);
+        if (rc != MICKEY_OK) return rc;
+    }
+    return ok();
+}
+
+int mickey_batch_get_routing(const mickey_batch *b, uint64_t *threshold, size_t *latency_requests,
+                             double *latency_clock_ratio)
+{
+    if (!b) return fail(MICKEY_EINVAL, "mickey_batch_get_routing: NULL batch");
+    if (threshold) *threshold = b->lat_threshold;
+    if (latency_requests) *latency_requests = b->nlat;
+    if (latency_clock_ratio) *latency_clock_ratio = b->lat_ratio;
+    return ok();
+}
+
 int mickey_batch_autotune(mickey_batch *b, uint64_t cap_bits, const char *cache_path)
 {
     if (!b) return fail(MICKEY_EINVAL, "mickey_batch_autotune: NULL batch");
@@ -383,10 +571,14 @@ int mickey_batch_autotune(mickey_batch *b, uint64_t cap_bits, const char *cache_
     (void)hipGetDevice(&dev);
     hipDeviceProp_t prop;
     const char *arch = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.gcnArchName : "unknown";
+    std::vector<uint64_t> capped(b->nreq);
     uint64_t capped_total = 0, capped_max = 0;
-    for (uint64_t nb : b->nbits) {
-        capped_total += std::min(nb, cap_bits);
-        capped_max = std::max(capped_max, std::min(nb, cap_bits));
+    size_t words = 0;
+    for (size_t r = 0; r < b->nreq; r++) {
+        capped[r] = std::min(b->nbits[r], cap_bits);
+        capped_total += capped[r];
+        capped_max = std::max(capped_max, capped[r]);
+        words += capped[r] / 32;
     }
     char sig[256];
     snprintf(sig, sizeof sig, "%s/nreq=%zu/cap=%llu/total=%llu/max=%llu", arch, b->nreq, (unsigned long long)cap_bits,
@@ -398,20 +590,21 @@ int mickey_batch_autotune(mickey_batch *b, uint64_t cap_bits, const char *cache_
             fclose(f);
             buf[len] = 0;
             int u = 0, w = 0;
+            double ratio = 0;
             const char *ps = strstr(buf, "\"signature\": \"");
             const char *pu = strstr(buf, "\"unroll\": ");
             const char *pw = strstr(buf, "\"waves_per_block\": ");
-            if (ps && pu && pw && strncmp(ps + 14, sig, strlen(sig)) == 0 && ps[14 + strlen(sig)] == '"' &&
-                sscanf(pu + 10, "%d", &u) == 1 && sscanf(pw + 19, "%d", &w) == 1 && find_variant(u, w))
-                return mickey_batch_set_params(b, u, w);
+            const char *pr = strstr(buf, "\"latency_clock_ratio\": ");
+            if (ps && pu && pw && pr && strncmp(ps + 14, sig, strlen(sig)) == 0 && ps[14 + strlen(sig)] == '"' &&
+                sscanf(pu + 10, "%d", &u) == 1 && sscanf(pw + 19, "%d", &w) == 1 && sscanf(pr + 23, "%lf", &ratio) == 1 &&
+                find_variant(u, w) && ratio > 0) {
+                b->unroll = u;
+                b->wpb = w;
+                b->lat_ratio = ratio;
+                int rc = prepare(b);
+                return rc == MICKEY_OK ? ok() : rc;
+            }
         }
-    }
-    // scratch outputs for the capped run
-    std::vector<uint64_t> capped(b->nreq);
-    size_t words = 0;
-    for (size_t r = 0; r < b->nreq; r++) {
-        capped[r] = std::min(b->nbits[r], cap_bits);
-        words += capped[r] / 32;
     }
     uint32_t *scratch = nullptr;
     if (hipMalloc(&scratch, std::max<size_t>(words, 1) * 4) != hipSuccess) {
@@ -423,29 +616,21 @@ int mickey_batch_autotune(mickey_batch *b, uint64_t cap_bits, const char *cache_
         souts[r] = scratch + w;
         w += capped[r] / 32;
     }
-    int rc = upload_meta(b, capped, souts);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (rc == MICKEY_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
-        rc = check_launch("hipEventCreate");
+    int rc = MICKEY_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = check_launch("hipEventCreate");
+    // 1. bitsliced variants, every request bitsliced
     float best_ms = 0;
     const Variant *best = nullptr;
     std::string timings;
+    if (rc == MICKEY_OK) {
+        route(b, capped, ~0ull);
+        rc = upload_meta(b, capped, souts);
+    }
     for (const Variant &v : kVariants) {
         if (rc != MICKEY_OK) break;
-        rc = enqueue(b, v);  // warm-up (code load)
-        float ms = 1e30f;
-        for (int rep = 0; rep < 2 && rc == MICKEY_OK; rep++) {
-            (void)hipEventRecord(e0, b->stream);
-            rc = enqueue(b, v);
-            (void)hipEventRecord(e1, b->stream);
-            if (rc == MICKEY_OK && hipEventSynchronize(e1) == hipSuccess) {
-                float t = 0;
-                (void)hipEventElapsedTime(&t, e0, e1);
-                ms = std::min(ms, t);
-            } else if (rc == MICKEY_OK) {
-                rc = check_launch("autotune timing");
-            }
-        }
+        float ms = 0;
+        rc = time_enqueue(b, v, e0, e1, &ms);
         if (rc != MICKEY_OK) break;
         char item[64];
         snprintf(item, sizeof item, "%s\"u%dw%d\": %.4f", timings.empty() ? "" : ", ", v.unroll, v.wpb, ms);
@@ -455,23 +640,36 @@ int mickey_batch_autotune(mickey_batch *b, uint64_t cap_bits, const char *cache_
             best_ms = ms;
         }
     }
+    // 2. the same requests, every one in latency mode (up to the lane limit): the ratio
+    //    of per-clock times of the two engines sets the automatic routing threshold
+    float lat_ms = 0;
+    if (rc == MICKEY_OK) {
+        route(b, capped, 1);
+        rc = upload_meta(b, capped, souts);
+        if (rc == MICKEY_OK && b->ngroups == 0) rc = time_enqueue(b, *best, e0, e1, &lat_ms);
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(b->stream);
     (void)hipFree(scratch);
-    const int rc2 = upload_meta(b, b->nbits, b->outs);  // restore the real outputs
+    if (rc == MICKEY_OK && best) {
+        b->unroll = best->unroll;
+        b->wpb = best->wpb;
+        if (lat_ms > 0 && best_ms > 0) b->lat_ratio = lat_ms / best_ms;
+    }
+    const int rc2 = prepare(b);  // restore the real requests, routing and graph
     if (rc != MICKEY_OK) return rc;
     if (rc2 != MICKEY_OK) return rc2;
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "w")) {
             fprintf(f,
                     "{\"signature\": \"%s\", \"unroll\": %d, \"waves_per_block\": %d, \"word_bits\": 32, "
-                    "\"best_ms\": %.4f, \"timings_ms\": {%s}}\n",
-                    sig, best->unroll, best->wpb, best_ms, timings.c_str());
+                    "\"latency_clock_ratio\": %.5f, \"best_ms\": %.4f, \"latency_ms\": %.4f, \"timings_ms\": {%s}}\n",
+                    sig, b->unroll, b->wpb, b->lat_ratio, best_ms, lat_ms, timings.c_str());
             fclose(f);
         }
     }
-    return mickey_batch_set_params(b, best->unroll, best->wpb);
+    return ok();
 }
 
 void mickey_batch_free(mickey_batch *b) { destroy(b); }

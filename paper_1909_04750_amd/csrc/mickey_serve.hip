@@ -84,10 +84,12 @@ __device__ __forceinline__ void write_back_lane(const Regs<1> &x, uint32_t l, ui
     for (int b = 0; b < 25; b++) dst[b] = (uint8_t)(w[b >> 2] >> (24 - 8 * (b & 3)));
 }
 
-// One quantum of nblocks*32 clocks on every slice with an occupied lane bit.  Per-lane
-// output pointers and remaining word counts live in LDS for the quantum.  When a lane's
-// request ends at the end of a block, its state is packed back into the pool there and
-// the lane is appended to the completion list.
+// One quantum of nblocks*32 clocks on every slice with an occupied lane bit.  Each
+// lane's output pointer and remaining words are read once into LDS; during the quantum
+// lane l stores block blk's word at out[l] + blk while blk < left[l], so the per-block
+// bookkeeping is read-only.  When a lane's request ends at the end of a block, its state
+// is packed back into the pool right there and the lane is appended to the completion
+// list; at the end of the quantum the pointers and counts move on by the blocks done.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void quantum_kernel(
     uint32_t *__restrict__ planes, uint32_t nslices, uint32_t nblocks, uint32_t **lane_out,
     uint32_t *__restrict__ lane_left, const uint32_t *__restrict__ lane_sid, uint8_t *__restrict__ pool,
@@ -99,30 +101,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     const uint32_t tid = threadIdx.x;
     const uint32_t g = blockIdx.x * 64u + tid;
     if (g >= nslices) return;  // no barriers: each lane touches only its own LDS columns
-    uint32_t active = 0;
+    uint32_t active = 0, ends = 0;  // lanes with words left; lanes that end in this quantum
     for (int l = 0; l < 32; l++) {
         const uint32_t left = lane_left[g * 32u + l];
         s_left[l][tid] = left;
         s_out[l][tid] = lane_out[g * 32u + l];
         active |= (left ? 1u : 0u) << l;
+        ends |= (left && left <= nblocks ? 1u : 0u) << l;
     }
     if (!active) return;
     const size_t pitch = (size_t)nslices * 4u;
     const uint32_t voff = g * 4u;
     Regs<1> x;
     load_state<1>(x, planes, pitch, voff);
-    for (uint32_t blk = 0; blk < nblocks && active; blk++) {
-        uint32_t finished = 0;
+    uint32_t blk = 0;
+    for (; blk < nblocks && active; blk++) {
         rowmajor_block<kServeUnroll>(x, zbuf, tid, [&](int l, uint32_t w) {
-            if ((active >> l) & 1u) {
-                uint32_t *o = s_out[l][tid];
-                *o = w;
-                s_out[l][tid] = o + 1;
-                const uint32_t left = s_left[l][tid] - 1u;
-                s_left[l][tid] = left;
-                if (!left) finished |= 1u << l;
-            }
+            if ((active >> l) & 1u) s_out[l][tid][blk] = w;
         });
+        uint32_t finished = 0;
+        if (ends) {
+            for (uint32_t l = 0; l < 32; l++)
+                if (((ends >> l) & 1u) && s_left[l][tid] == blk + 1u) finished |= 1u << l;
+        }
         if (finished) {
             for (uint32_t l = 0; l < 32; l++) {
                 if ((finished >> l) & 1u) {
@@ -135,8 +136,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     }
     store_state<1>(x, planes, pitch, voff);
     for (int l = 0; l < 32; l++) {
-        lane_left[g * 32u + l] = s_left[l][tid];
-        lane_out[g * 32u + l] = s_out[l][tid];
+        const uint32_t left = s_left[l][tid];
+        if (!left) continue;
+        const uint32_t done = left < blk ? left : blk;
+        lane_left[g * 32u + l] = left - done;
+        lane_out[g * 32u + l] = s_out[l][tid] + done;
     }
 }
 

@@ -21,6 +21,7 @@ EXPORTED = [
     "mickey_sync", "mickey_last_error", "mickey_last_error_message", "mickey_ops_per_clock",
     "mickey_batch_create", "mickey_batch_set", "mickey_batch_run", "mickey_batch_sync", "mickey_batch_stream",
     "mickey_batch_set_params", "mickey_batch_get_params", "mickey_batch_autotune", "mickey_batch_free",
+    "mickey_batch_set_latency_threshold", "mickey_batch_get_routing",
     "mickey_server_create", "mickey_server_submit", "mickey_server_step", "mickey_server_poll",
     "mickey_server_result", "mickey_server_copy", "mickey_server_release", "mickey_server_stats",
     "mickey_server_state", "mickey_server_stream", "mickey_server_free", "mickey_server_submit_many",
@@ -96,6 +97,10 @@ def load_library():
     L.mickey_batch_autotune.restype = i
     L.mickey_batch_free.argtypes = [vp]
     L.mickey_batch_free.restype = None
+    L.mickey_batch_set_latency_threshold.argtypes = [vp, u64]
+    L.mickey_batch_set_latency_threshold.restype = i
+    L.mickey_batch_get_routing.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_double)]
+    L.mickey_batch_get_routing.restype = i
     L.mickey_server_create.argtypes = [vp, sz, ctypes.c_uint32, u64, vp]
     L.mickey_server_create.restype = vp
     L.mickey_server_submit.argtypes = [vp, ctypes.c_uint32, u64]
@@ -313,6 +318,18 @@ class Batch:
         u, w = ctypes.c_int(0), ctypes.c_int(0)
         _check(load_library().mickey_batch_get_params(self._h, ctypes.byref(u), ctypes.byref(w)))
         return u.value, w.value
+
+    LATENCY_OFF = (1 << 64) - 1
+
+    def set_latency_threshold(self, bits: int) -> None:
+        """0: automatic size-aware routing; LATENCY_OFF: all bitsliced; else a threshold."""
+        _check(load_library().mickey_batch_set_latency_threshold(self._h, int(bits)))
+
+    def routing(self):
+        """(threshold in bits or None, requests in latency mode, latency/bitsliced clock ratio)"""
+        t, n, r = ctypes.c_uint64(0), ctypes.c_size_t(0), ctypes.c_double(0)
+        _check(load_library().mickey_batch_get_routing(self._h, ctypes.byref(t), ctypes.byref(n), ctypes.byref(r)))
+        return (None if t.value == self.LATENCY_OFF else int(t.value)), int(n.value), float(r.value)
 
     def autotune(self, cap_bits: int, cache_path=None):
         _check(load_library().mickey_batch_autotune(

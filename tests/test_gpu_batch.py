@@ -180,3 +180,31 @@ def test_batch_10k_recipe_capped_sampled_parity():
     want = oracle_words(keys[sample], ivs[sample], ivb[sample], nbits[sample])
     for k, i in enumerate(sample):
         assert (got[i] == want[k]).all(), int(i)
+
+
+def test_latency_mode_matches_bitsliced_and_oracle():
+    keys, ivs, ivb, nbits = random_requests(8, 260, 120)
+    nbits[:4] = [0, 32, 120 * 32, 64]
+    b = mickey.Batch(len(nbits))
+    arena, offs, ptrs = arena_for(nbits)
+    b.set(to_dev(keys), to_dev(ivs), to_dev(ivb), nbits, ptrs)
+    outs = {}
+    for th in (mickey.Batch.LATENCY_OFF, 1, 32 * 60, 0):
+        b.set_latency_threshold(th)
+        arena.zero_()
+        torch.cuda.synchronize()
+        b.run()
+        b.sync()
+        outs[th] = arena.cpu().numpy().view(np.uint32).copy()
+        t, nlat, ratio = b.routing()
+        if th == mickey.Batch.LATENCY_OFF:
+            assert t is None and nlat == 0
+        elif th == 1:
+            assert nlat == int((nbits > 0).sum())  # every non-empty request in latency mode
+        elif th == 32 * 60:
+            assert nlat == int((nbits >= th).sum()) and 0 < nlat < len(nbits)
+    for th, o in outs.items():
+        assert (o == outs[mickey.Batch.LATENCY_OFF]).all(), th
+    want = np.concatenate(oracle_words(keys, ivs, ivb, nbits))
+    assert (outs[1][: len(want)] == want).all()
+    b.close()
