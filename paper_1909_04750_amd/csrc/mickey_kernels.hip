@@ -71,8 +71,8 @@ gen_bitsliced_kernel(uint32_t *__restrict__ state, uint32_t ngroups, uint32_t pi
     Regs<K> x;
     load_state<K>(x, state, pitch, voff);
     char *plane = (char *)out;
-    uint64_t t = 0;
-    for (; t + kUnroll <= nbits; t += kUnroll) {
+    // count down to zero: the loop test is a scalar 64-bit compare
+    for (uint64_t it = nbits / kUnroll; it != 0; --it) {
 #pragma unroll
         for (int u = 0; u < kUnroll; u++) {
             st_word<K>(plane + voff, x.r[0] ^ x.s[0]);
@@ -80,7 +80,7 @@ gen_bitsliced_kernel(uint32_t *__restrict__ state, uint32_t ngroups, uint32_t pi
             clock_gen<K>(x);
         }
     }
-    for (; t < nbits; t++) {
+    for (uint64_t t = nbits - nbits % kUnroll; t < nbits; t++) {
         st_word<K>(plane + voff, x.r[0] ^ x.s[0]);
         plane += pitch;
         clock_gen<K>(x);
