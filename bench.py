@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("csrc/mickey_bitslice.h", "csrc/mickey_kernels.hip"):
+    for f in ("csrc/mickey_bitslice.h", "csrc/mickey_device.h", "csrc/mickey_kernels.hip"):
         h.update(open(os.path.join(ROOT, "paper_1909_04750_amd", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -182,13 +182,18 @@ def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 
                                   "batch_speedup": round(serial_ms / batch_ms, 1)}}
 
 
-def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, rate: float = 20000.0,
-                nstates: int = 10 ** 6, budget: int = 64 << 30, sat_bytes: int = 56 << 10, sat_seconds: float = 3.0):
+def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: float, rate: float = 20000.0,
+                nstates: int = 10 ** 6, budget: int = 64 << 30, chunk: int = 64 << 10, sat_bytes: int = 56 << 10,
+                sat_seconds: float = 3.0, nverify: int = 16):
     """Served generation over 10^6 resident states (splitmix64 seed 5 keys and 80-bit
     IVs, initialised).  Open loop: Poisson arrivals at `rate`/s for `duration` s, state
-    uniform, size log-uniform in [4 KiB, max_bytes]; latency = completion - scheduled
-    arrival.  Closed loop (saturation): every state keeps one sat_bytes request in flight
-    for sat_seconds; compared with the plain kernel on the same 10^6 instances."""
+    uniform, size log-uniform in [4 KiB, max_bytes], delivered in `chunk`-byte chunks
+    through a `budget`-byte output budget; latency = completion of the last chunk -
+    scheduled arrival.  The run stops when every request is done or `drain` s after the
+    last arrival; requests still running then are censored (their latency is only known
+    to exceed the time they have waited).  Closed loop (saturation): every state keeps one
+    sat_bytes request in flight for sat_seconds; compared with the plain kernel on the
+    same 10^6 instances."""
     keys, ivs = synth.keys_ivs(5, nstates)
     dk, dv = torch.from_numpy(keys).cuda(), torch.from_numpy(ivs).cuda()
     init = mickey.Mickey(dk, dv)
@@ -197,43 +202,105 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, rate: flo
     # -- open loop
     t_arr, sids, nbits = synth.serve_requests(5, nstates, rate, duration, 4096, max_bytes)
     n = len(t_arr)
-    srv = mickey.Server(init, nslices=2048, quantum_clocks=2048, budget_bytes=budget)
-    lat = np.zeros(n)
+    # sampled for the bit-exact check: first requests on their state, at most 256 KiB
+    first = np.unique(sids, return_index=True)[1]
+    cand = first[nbits[first] <= 8 * (256 << 10)]
+    verify = set(np.sort(cand)[:: max(1, len(cand) // nverify)][:nverify].tolist())
+    vwords = {k: [] for k in verify}
+    nslices, qclocks = 32768, 2048
+    srv = mickey.Server(init, nslices=nslices, quantum_clocks=qclocks, budget_bytes=budget)
+    srv.set_chunk(chunk)
+    lat = np.full(n, np.inf)
+    run_s = np.zeros(n)  # admission to completion
     t0 = time.monotonic_ns()
     i = done_n = 0
     last_done = t0
+    nchunks = 0
+    peak_running = 0
+    t_stop = duration + drain
+    next_note = 5.0
     while done_n < n:
         now = (time.monotonic_ns() - t0) * 1e-9
+        if now > t_stop:
+            break
+        if now > next_note:
+            print("#   serve open loop t=%.0f s: %d/%d done" % (now, done_n, n), file=sys.stderr, flush=True)
+            next_note += 5.0
         k = int(np.searchsorted(t_arr, now, side="right"))
         if k > i:
             srv.submit_many(sids[i:k], nbits[i:k])  # ids are assigned in arrival order
             i = k
         srv.step()
-        ids = srv.poll()
+        ch = srv.poll_chunks(1 << 16)
+        if len(ch):
+            nchunks += len(ch)
+            for c in ch[np.isin(ch["request"], list(verify))] if verify else ():
+                buf = torch.empty(int(c["words"]), dtype=torch.int32, device="cuda")
+                srv.copy_chunk(int(c["handle"]), buf, int(c["words"]))
+                vwords[int(c["request"])].append((int(c["offset"]), buf.cpu().numpy().view(np.uint32)))
+            srv.release_chunks(ch["handle"])  # the consumer has taken the chunk
+        ids = srv.poll(1 << 16)
         if len(ids):
             tm = srv.times_many(ids)
             lat[ids] = (tm[:, 2].astype(np.float64) - t0) * 1e-9 - t_arr[ids]
+            run_s[ids] = (tm[:, 2].astype(np.float64) - tm[:, 1].astype(np.float64)) * 1e-9
             last_done = max(last_done, int(tm[:, 2].max()))
-            srv.release_many(ids)
             done_n += len(ids)
-        elif i == n and srv.stats()["running"] == 0 and srv.stats()["waiting"] == 0:
+        st = srv.stats()
+        peak_running = max(peak_running, st["running"])
+        if not len(ch) and not len(ids) and i == n and st["running"] == 0 and st["waiting"] == 0:
             srv.wait()
+    t_end = time.monotonic_ns()
     st = srv.stats()
     srv.close()
-    span = (last_done - t0) * 1e-9
-    total = int(nbits.sum())
+    span = (t_end - t0) * 1e-9
+    done = np.isfinite(lat)
+    cens = np.where(done, lat, span - t_arr)  # a censored request has waited at least this long
+
+    def pct(q):
+        v = float(np.percentile(lat, q))
+        return (round(v, 4) if np.isfinite(v) else None), round(float(np.percentile(cens, q)), 4)
+    p50, p50_lb = pct(50)
+    p99, p99_lb = pct(99)
+    # per-request stream rate (bits / (completion - admission)) of completed requests of >= 1 MiB
+    big = done & (nbits >= 8 * (1 << 20))
+    rate_mbit = round(float(np.median(nbits[big] / run_s[big])) / 1e6, 3) if big.any() else None
+    # sampled requests (first request on their state) against the plain kernel run from the
+    # same keys and IVs (the plain path is the one tested bit-exact against the oracle)
+    checked = mism = 0
+    vk = sorted(k for k in verify if done[k])
+    if vk:
+        ln = int(max(nbits[k] for k in vk))
+        ref = mickey.Mickey(torch.from_numpy(keys[sids[vk]]).cuda(), torch.from_numpy(ivs[sids[vk]]).cuda())
+        rbuf = torch.empty((len(vk), ln // 32), dtype=torch.int32, device="cuda")
+        ref.generate(ln, mickey.ROWMAJOR_U32, rbuf)
+        ref.sync()
+        want_all = rbuf.cpu().numpy().view(np.uint32)
+        ref.close()
+        for j, k in enumerate(vk):
+            words = np.concatenate([w for _, w in sorted(vwords[k], key=lambda t: t[0])])
+            checked += 1
+            mism += int(not np.array_equal(words, want_all[j, : int(nbits[k]) // 32]))
     out["open_loop"] = {
         "workload": "10^6 resident states; Poisson arrivals %.0f/s for %.1f s; state uniform; size log-uniform "
-                    "4 KiB..%d KiB (configured range 4 KiB..64 MiB, cut for bench time); row-major u32 output; "
-                    "64 GiB output budget; 2048 slots x 32 lanes; quantum 2048 clocks" % (rate, duration, max_bytes >> 10),
-        "requests": n, "total_bits": total, "span_s": round(span, 3),
-        "served_gbit_s": round(total / span / 1e9, 3), "offered_gbit_s": round(total / duration / 1e9, 3),
-        "latency_s": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
-                      "max": round(float(lat.max()), 4)},
-        "steps": st["steps"], "mean_quantum_ms": round(st["quantum_ns"] / max(st["steps"], 1) / 1e6, 3),
+                    "4 KiB..%d KiB; row-major u32 output delivered in %d KiB chunks; 64 GiB output budget; "
+                    "%d slots x 32 lanes; quantum %d clocks; stopped %.0f s after the last arrival" % (
+                        rate, duration, max_bytes >> 10, chunk >> 10, nslices, qclocks, drain),
+        "requests": n, "completed": int(done.sum()), "completed_fraction": round(float(done.mean()), 4),
+        "bits_offered": int(nbits.sum()), "bits_delivered": st["bits_delivered"], "span_s": round(span, 3),
+        "served_gbit_s": round(st["bits_delivered"] / span / 1e9, 3),
+        "offered_gbit_s": round(float(nbits.sum()) / duration / 1e9, 3),
+        "latency_s": {"p50": p50, "p99": p99, "p50_lower_bound": p50_lb, "p99_lower_bound": p99_lb,
+                      "max_completed": round(float(lat[done].max()), 4) if done.any() else None},
+        "stream_rate_mbit_s_per_request": rate_mbit,
+        "chunks": nchunks, "peak_running": peak_running, "steps": st["steps"],
+        "mean_quantum_ms": round(st["quantum_ns"] / max(st["steps"], 1) / 1e6, 3),
+        "same_as_plain_kernel_sample": {"requests": checked, "mismatches": mism,
+                                        "sample": "first request on its state, at most 256 KiB, spread over the "
+                                                  "arrivals, compared with the plain row-major kernel"},
     }
-    print("# serve open loop: %d requests, p50 %.3f s p99 %.3f s" % (n, out["open_loop"]["latency_s"]["p50"],
-          out["open_loop"]["latency_s"]["p99"]), file=sys.stderr, flush=True)
+    print("# serve open loop: %d/%d requests done, p50 %s s p99 %s s (lower bound %.1f s)" % (
+        int(done.sum()), n, p50, p99, p99_lb), file=sys.stderr, flush=True)
     # -- closed loop: every state busy
     sat_bits = 8 * sat_bytes
     srng = np.random.default_rng(55)
@@ -307,8 +374,26 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the 10,000-request batched measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the served measurements")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="Poisson arrival window of the served run")
-    ap.add_argument("--serve-max-kib", type=int, default=256, help="largest served request (KiB)")
+    ap.add_argument("--serve-max-kib", type=int, default=64 << 10, help="largest served request (KiB)")
+    ap.add_argument("--serve-drain", type=float, default=30.0,
+                    help="seconds the open-loop served run continues after the last arrival")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
     args = ap.parse_args()
+    if args.source_hash:
+        print(kernel_source_hash())
+        return 0
+    if args.copy_calib:
+        import torch
+        a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")  # 1 GiB
+        a.fill_(7)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": a.numel() * 4, "launches": 3}))
+        return 0
     if args.gpus != 1:
         print("bench.py measures one GPU only: the instances are independent, so more GPUs "
               "would only partition them (no collectives); run with --gpus 1", file=sys.stderr)
@@ -433,7 +518,8 @@ def main() -> int:
     if not args.no_batch:
         res["batch_10k"] = bench_batch(torch, mickey, synth)
     if not args.no_serve:
-        res["serve"] = bench_serve(torch, mickey, synth, args.serve_seconds, args.serve_max_kib << 10)
+        res["serve"] = bench_serve(torch, mickey, synth, args.serve_seconds, args.serve_max_kib << 10,
+                                   args.serve_drain)
     print(json.dumps(res), flush=True)
     return 0
 

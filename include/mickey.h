@@ -223,7 +223,8 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
                                     uint64_t budget_bytes, void *hip_stream);
 
 /* Queue a request: resume state `state_id` for nbits keystream bits (a positive multiple
- * of 32).  Returns the request id (>= 0) or a negative error code. */
+ * of 32, at most 2^40; with whole-request delivery the output must also fit the budget
+ * and 2^32 words).  Returns the request id (>= 0) or a negative error code. */
 int64_t mickey_server_submit(mickey_server *s, uint32_t state_id, uint64_t nbits);
 
 /* Batched forms: submit n requests (ids[k] gets the id or a negative code), release n
@@ -246,6 +247,36 @@ int mickey_server_wait(mickey_server *s);
 /* Ids of requests completed since the last call (at most cap); returns the count. */
 int64_t mickey_server_poll(mickey_server *s, uint64_t *ids, size_t cap);
 
+/* Chunked delivery.  After mickey_server_set_chunk(s, c) (c a multiple of 4 bytes that
+ * fits the budget; 0 restores whole-request delivery), new submissions are delivered in
+ * consecutive chunks of c bytes (the last one shorter).  A request then reserves only
+ * one chunk of the budget at a time, so its total size is bounded by the 2^40-bit limit
+ * rather than by the budget.  Its state stays reserved for it between chunks, so requests
+ * on a state still run in arrival order, and each chunk continues the keystream at the
+ * exact bit where the previous one stopped (the state is written back at the end of every
+ * chunk, as at the end of a request).
+ *
+ * mickey_server_poll_chunks() returns the chunks finished since the last call, in
+ * completion order (chunks of one request in stream order).  Their words stay valid until
+ * the caller gives them back with mickey_server_release_chunks(); until then they count
+ * against the budget.  A chunked request also appears in mickey_server_poll() when its
+ * last chunk is done; mickey_server_result()/copy()/release() do not apply to it. */
+typedef struct mickey_chunk {
+    uint64_t request; /* request id */
+    uint64_t handle;  /* give back with mickey_server_release_chunks() */
+    uint64_t offset;  /* index of the chunk's first word in the request's stream */
+    uint64_t words;   /* 32-bit words in the chunk */
+    uint32_t *out;    /* device pointer to the words (MICKEY_ROWMAJOR_U32 layout) */
+    uint64_t last;    /* nonzero when this chunk completes the request */
+} mickey_chunk;
+
+int mickey_server_set_chunk(mickey_server *s, uint64_t chunk_bytes);
+int64_t mickey_server_poll_chunks(mickey_server *s, mickey_chunk *out, size_t cap);
+int mickey_server_release_chunks(mickey_server *s, const uint64_t *handles, size_t n);
+/* Copy the first nwords words of a delivered, not yet released chunk into dst (device);
+ * synchronous. */
+int mickey_server_copy_chunk(const mickey_server *s, uint64_t handle, uint32_t *dst, uint64_t nwords);
+
 /* A completed request's output (device, nbits/32 words in the MICKEY_ROWMAJOR_U32 layout
  * of one instance) and its arrival / admission / completion times (ns, steady clock).
  * MICKEY_ERANGE (and *out = NULL) if it was refused for passing 2^40 bits. */
@@ -258,7 +289,8 @@ int mickey_server_copy(const mickey_server *s, uint64_t id, uint32_t *dst, uint6
 /* Return a completed request's output space to the budget (its words become invalid). */
 int mickey_server_release(mickey_server *s, uint64_t id);
 
-/* [0] waiting, [1] running, [2] admitted, [3] finished, [4] steps, [5] quantum time in
+/* [0] waiting (including chunked requests between two chunks), [1] running, [2] admitted,
+ * [3] finished, [4] steps, [5] quantum time in
  * ns (launch to retirement), [6] keystream bits delivered, [7] free budget in 32-bit
  * words, [8] host ns blocked on quanta, [9] host ns retiring, [10] host ns admitting. */
 int mickey_server_stats(const mickey_server *s, uint64_t out[11]);

@@ -7,12 +7,22 @@
 //   1. retires requests that completed in the last quantum (their state was written
 //      back to the pool by the kernel at the exact clock where the request ended),
 //   2. admits waiting requests, in arrival order, into free lane bits while the output
-//      budget allows (a request reserves its whole output; a state runs at most one
-//      request at a time, so requests on one state run in arrival order),
+//      budget allows (a request reserves its whole output, or in chunked delivery one
+//      chunk at a time; a state runs at most one request at a time, so requests on one
+//      state run in arrival order),
 //   3. gathers the admitted states into their lane bits, and
 //   4. runs one quantum of Q clocks on every occupied slice, writing each request's
 //      keystream as row-major words (MICKEY_ROWMAJOR_U32 layout) into its output.
 // Requests that arrive while others run join at the next quantum, next to them.
+//
+// Chunked delivery: a request submitted after mickey_server_set_chunk(c) runs as a
+// sequence of admissions of at most c bytes each.  Each admission reserves only its own
+// chunk, and its lane writes the state back when the chunk ends (the same exact
+// write-back as at the end of a request), so the next chunk resumes at the next bit.  The
+// state stays reserved for the request between its chunks, and requests that are
+// between chunks are admitted before new ones.  The client reads each finished chunk
+// and gives its space back, so the budget bounds the output in flight, not the size of
+// a request.
 #include "mickey_device.h"
 #include "mickey_host.h"
 
@@ -149,11 +159,22 @@ struct Request {
     uint32_t sid;
     uint64_t nbits;
     uint64_t arrival_ns;
-    uint64_t admit_ns = 0, done_ns = 0;
+    uint64_t admit_ns = 0, first_ns = 0, done_ns = 0;  // first admission, first chunk done, last done
     uint32_t lane = kNoRequest;
-    size_t out_off = 0;  // word offset in the arena
+    uint32_t chunk_words = 0;  // 0: whole-request delivery
+    size_t out_off = 0;        // word offset in the arena of the output (or current chunk)
+    uint64_t words_admitted = 0, words_done = 0;
+    uint32_t cur_words = 0;    // words of the admission in flight
+    bool refused = false;      // passed 2^40 bits
     bool done = false;
     bool released = false;
+};
+
+// A delivered chunk's arena block, by handle.
+struct ChunkSlot {
+    size_t off = 0;
+    uint64_t words = 0;
+    bool live = false;
 };
 
 // Output-arena allocator, in 32-bit words: released blocks go to exact-size free lists
@@ -271,6 +292,11 @@ struct mickey_server {
     std::vector<Request> reqs;     // by id
     std::vector<uint64_t> lane_req;
     std::vector<uint64_t> completed;  // not yet reported
+    uint32_t chunk_words = 0;         // chunk size of new submissions (0: whole requests)
+    std::deque<uint64_t> continuing;  // chunked requests between two chunks, oldest first
+    std::vector<mickey_chunk> ready;  // delivered chunks not yet polled
+    std::vector<ChunkSlot> slots;     // chunk handles
+    std::vector<uint64_t> free_slots;
     uint64_t steps = 0, quanta_ns = 0, admitted = 0, finished = 0, bits_done = 0;
     uint64_t ns_wait = 0, ns_retire = 0, ns_admit = 0;  // host time spent in each part
 };
@@ -316,27 +342,78 @@ int retire_oldest(mickey_server *s)
     for (uint32_t k = 0; k < ndone; k++) {
         const uint32_t lane = list[k];
         Request &r = s->reqs[s->lane_req[lane]];
-        r.done = true;
-        r.done_ns = t1;
-        s->state_bits[r.sid] += r.nbits;
-        s->state_busy[r.sid] = 0;
         s->lane_req[lane] = ~0ull;
         s->free_lanes.push_back(lane);
+        r.lane = kNoRequest;
+        r.words_done += r.cur_words;
+        s->state_bits[r.sid] += 32ull * r.cur_words;
+        s->bits_done += 32ull * r.cur_words;
+        if (!r.first_ns) r.first_ns = t1;
+        const bool last = r.words_done == r.nbits / 32;
+        if (r.chunk_words) {
+            uint64_t h;
+            if (!s->free_slots.empty()) {
+                h = s->free_slots.back();
+                s->free_slots.pop_back();
+            } else {
+                h = s->slots.size();
+                s->slots.emplace_back();
+            }
+            s->slots[h] = ChunkSlot{r.out_off, r.cur_words, true};
+            s->ready.push_back(mickey_chunk{r.id, h, r.words_done - r.cur_words, r.cur_words, s->arena + r.out_off,
+                                            last ? 1ull : 0ull});
+        }
+        r.cur_words = 0;
+        if (!last) {
+            s->continuing.push_back(r.id);  // the state stays reserved for this request
+            continue;
+        }
+        r.done = true;
+        r.done_ns = t1;
+        s->state_busy[r.sid] = 0;
         s->completed.push_back(r.id);
         s->finished++;
-        s->bits_done += r.nbits;
     }
     s->ns_retire += now_ns() - t1;
     return MICKEY_OK;
 }
 
-// Decide admissions in arrival order into s->hadm (enqueued by the next step); requests
-// on busy states keep their place.
+// Admit the next part of request r (its whole output, or its next chunk) into a free lane
+// if a lane and the budget allow; false if either is full.
+bool admit_next(mickey_server *s, Request &r, uint64_t t_admit)
+{
+    const uint64_t left = r.nbits / 32 - r.words_admitted;
+    const uint32_t words = r.chunk_words ? (uint32_t)std::min<uint64_t>(left, r.chunk_words) : (uint32_t)left;
+    size_t off = 0;
+    if (s->free_lanes.empty() || !s->alloc.alloc(words, &off)) return false;
+    const uint32_t lane = s->free_lanes.back();
+    s->free_lanes.pop_back();
+    r.lane = lane;
+    r.out_off = off;
+    r.cur_words = words;
+    r.words_admitted += words;
+    if (!r.admit_ns) r.admit_ns = t_admit;
+    s->lane_req[lane] = r.id;
+    s->hadm[s->pending++] = Admit{lane, r.sid, words, 0u, s->arena + off};
+    s->admitted++;
+    return true;
+}
+
+// Decide admissions into s->hadm (enqueued by the next step): first the chunked requests
+// that are between two chunks (oldest first), then waiting requests in arrival order;
+// requests on busy states keep their place.
 void decide_admissions(mickey_server *s)
 {
     const uint64_t t_admit = now_ns();
-    std::deque<uint64_t> keep;
     bool full = false;
+    while (!s->continuing.empty()) {
+        if (!admit_next(s, s->reqs[s->continuing.front()], t_admit)) {
+            full = true;
+            break;
+        }
+        s->continuing.pop_front();
+    }
+    std::deque<uint64_t> keep;
     for (uint64_t id : s->waiting) {
         Request &r = s->reqs[id];
         if (full || s->state_busy[r.sid]) {
@@ -345,26 +422,17 @@ void decide_admissions(mickey_server *s)
         }
         if (s->state_bits[r.sid] + r.nbits > MICKEY_MAX_BITS_PER_IV) {  // 2^40 per key/IV pair
             r.done = true;
+            r.refused = true;
             r.done_ns = t_admit;
-            r.lane = kNoRequest;
             s->completed.push_back(r.id);
             continue;
         }
-        size_t off = 0;
-        if (s->free_lanes.empty() || !s->alloc.alloc(r.nbits / 32, &off)) {  // slots or budget full
+        if (!admit_next(s, r, t_admit)) {  // slots or budget full
             full = true;
             keep.push_back(id);
             continue;
         }
-        const uint32_t lane = s->free_lanes.back();
-        s->free_lanes.pop_back();
-        r.lane = lane;
-        r.out_off = off;
-        r.admit_ns = t_admit;
         s->state_busy[r.sid] = 1;
-        s->lane_req[lane] = r.id;
-        s->hadm[s->pending++] = Admit{lane, r.sid, (uint32_t)(r.nbits / 32), 0u, s->arena + off};
-        s->admitted++;
     }
     s->waiting.swap(keep);
     s->ns_admit += now_ns() - t_admit;
@@ -452,12 +520,17 @@ int64_t mickey_server_submit(mickey_server *s, uint32_t state_id, uint64_t nbits
 {
     if (!s) return fail(MICKEY_EINVAL, "mickey_server_submit: NULL server");
     if (state_id >= s->nstates) return fail(MICKEY_EINVAL, "mickey_server_submit: state %u out of range", state_id);
-    if (nbits == 0 || nbits % 32 || nbits / 32 > s->alloc.capacity)
-        return fail(MICKEY_EINVAL, "mickey_server_submit: nbits must be k*32, 0 < k, within the budget");
+    if (nbits == 0 || nbits % 32 || nbits > MICKEY_MAX_BITS_PER_IV)
+        return fail(MICKEY_EINVAL, "mickey_server_submit: nbits must be k*32 with 0 < k, at most 2^40");
+    if (!s->chunk_words && (nbits / 32 > s->alloc.capacity || nbits / 32 > 0xffffffffull))
+        return fail(MICKEY_EINVAL,
+                    "mickey_server_submit: a whole-request output must fit the budget and 2^32 words "
+                    "(use chunked delivery)");
     Request r;
     r.id = s->reqs.size();
     r.sid = state_id;
     r.nbits = nbits;
+    r.chunk_words = s->chunk_words;
     r.arrival_ns = now_ns();
     s->reqs.push_back(r);
     s->waiting.push_back(r.id);
@@ -557,7 +630,7 @@ int mickey_server_times_many(const mickey_server *s, const uint64_t *ids, size_t
         const Request &r = s->reqs[ids[k]];
         out[3 * k] = r.arrival_ns;
         out[3 * k + 1] = r.admit_ns;
-        out[3 * k + 2] = r.lane == kNoRequest && !r.released ? 0 : r.done_ns;
+        out[3 * k + 2] = r.refused ? 0 : r.done_ns;
     }
     return ok();
 }
@@ -581,13 +654,16 @@ int mickey_server_result(const mickey_server *s, uint64_t id, uint32_t **out, ui
     const Request &r = s->reqs[id];
     if (!r.done) return fail(MICKEY_EINVAL, "mickey_server_result: request %llu not complete", (unsigned long long)id);
     if (r.released) return fail(MICKEY_EINVAL, "mickey_server_result: request %llu was released", (unsigned long long)id);
-    if (out) *out = r.lane == kNoRequest ? nullptr : s->arena + r.out_off;
+    if (out) *out = r.refused || r.chunk_words ? nullptr : s->arena + r.out_off;
     if (times_ns) {
         times_ns[0] = r.arrival_ns;
         times_ns[1] = r.admit_ns;
         times_ns[2] = r.done_ns;
     }
-    if (r.lane == kNoRequest) return fail(MICKEY_ERANGE, "request %llu would pass 2^40 bits", (unsigned long long)id);
+    if (r.refused) return fail(MICKEY_ERANGE, "request %llu would pass 2^40 bits", (unsigned long long)id);
+    if (r.chunk_words && out)
+        return fail(MICKEY_EINVAL, "mickey_server_result: request %llu was delivered in chunks",
+                    (unsigned long long)id);
     return ok();
 }
 
@@ -596,14 +672,15 @@ int mickey_server_release(mickey_server *s, uint64_t id)
 {
     if (!s || id >= s->reqs.size()) return fail(MICKEY_EINVAL, "mickey_server_release: unknown request");
     Request &r = s->reqs[id];
-    if (!r.done || r.lane == kNoRequest || r.released)
+    if (!r.done || r.refused || r.released || r.chunk_words)
         return fail(MICKEY_EINVAL, "mickey_server_release: nothing to release");
     s->alloc.release(r.out_off, r.nbits / 32);
     r.released = true;
     return ok();
 }
 
-// Counters: [0] waiting, [1] running, [2] admitted, [3] finished, [4] steps,
+// Counters: [0] waiting (with chunked requests between two chunks), [1] running,
+// [2] admitted, [3] finished, [4] steps,
 // [5] total quantum time (ns, launch to retirement), [6] keystream bits delivered,
 // [7] free budget words, [8] host ns blocked on quanta, [9] host ns retiring,
 // [10] host ns deciding admissions.
@@ -611,7 +688,7 @@ int mickey_server_stats(const mickey_server *s, uint64_t out[11])
 {
     if (!s || !out) return fail(MICKEY_EINVAL, "mickey_server_stats: bad argument");
     const size_t freew = s->alloc.free_words();
-    out[0] = s->waiting.size();
+    out[0] = s->waiting.size() + s->continuing.size();
     out[1] = s->nlanes - s->free_lanes.size();
     out[2] = s->admitted;
     out[3] = s->finished;
@@ -645,6 +722,56 @@ int mickey_server_copy(const mickey_server *s, uint64_t id, uint32_t *dst, uint6
     if (hipMemcpyAsync(dst, src, nwords * 4, hipMemcpyDeviceToDevice, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
         return check_launch("mickey_server_copy");
+    return ok();
+}
+
+int mickey_server_set_chunk(mickey_server *s, uint64_t chunk_bytes)
+{
+    if (!s) return fail(MICKEY_EINVAL, "mickey_server_set_chunk: NULL server");
+    if (chunk_bytes % 4 || chunk_bytes / 4 > s->alloc.capacity || chunk_bytes / 4 > 0xffffffffull)
+        return fail(MICKEY_EINVAL, "mickey_server_set_chunk: chunk must be whole 32-bit words within the budget");
+    s->chunk_words = (uint32_t)(chunk_bytes / 4);
+    return ok();
+}
+
+int64_t mickey_server_poll_chunks(mickey_server *s, mickey_chunk *out, size_t cap)
+{
+    if (!s || (!out && cap)) return fail(MICKEY_EINVAL, "mickey_server_poll_chunks: bad argument");
+    const size_t n = std::min(cap, s->ready.size());
+    std::copy(s->ready.begin(), s->ready.begin() + n, out);
+    s->ready.erase(s->ready.begin(), s->ready.begin() + n);
+    ok();
+    return (int64_t)n;
+}
+
+int mickey_server_release_chunks(mickey_server *s, const uint64_t *handles, size_t n)
+{
+    if (!s || (n && !handles)) return fail(MICKEY_EINVAL, "mickey_server_release_chunks: bad argument");
+    int first = MICKEY_OK;
+    for (size_t k = 0; k < n; k++) {
+        const uint64_t h = handles[k];
+        if (h >= s->slots.size() || !s->slots[h].live) {
+            if (first == MICKEY_OK)
+                first = fail(MICKEY_EINVAL, "mickey_server_release_chunks: handle %llu is not a delivered chunk",
+                             (unsigned long long)h);
+            continue;
+        }
+        s->alloc.release(s->slots[h].off, s->slots[h].words);
+        s->slots[h].live = false;
+        s->free_slots.push_back(h);
+    }
+    return first == MICKEY_OK ? ok() : first;
+}
+
+int mickey_server_copy_chunk(const mickey_server *s, uint64_t handle, uint32_t *dst, uint64_t nwords)
+{
+    if (!s || handle >= s->slots.size() || !s->slots[handle].live)
+        return fail(MICKEY_EINVAL, "mickey_server_copy_chunk: not a delivered chunk");
+    if (!dst || nwords > s->slots[handle].words) return fail(MICKEY_EINVAL, "mickey_server_copy_chunk: bad destination");
+    if (hipMemcpyAsync(dst, s->arena + s->slots[handle].off, nwords * 4, hipMemcpyDeviceToDevice, s->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+        return check_launch("mickey_server_copy_chunk");
     return ok();
 }
 

@@ -26,6 +26,8 @@ EXPORTED = [
     "mickey_server_result", "mickey_server_copy", "mickey_server_release", "mickey_server_stats",
     "mickey_server_state", "mickey_server_stream", "mickey_server_free", "mickey_server_submit_many",
     "mickey_server_release_many", "mickey_server_times_many", "mickey_server_wait",
+    "mickey_server_set_chunk", "mickey_server_poll_chunks", "mickey_server_release_chunks",
+    "mickey_server_copy_chunk",
 ]
 
 _lib = None
@@ -131,6 +133,14 @@ def load_library():
     L.mickey_server_times_many.restype = i
     L.mickey_server_wait.argtypes = [vp]
     L.mickey_server_wait.restype = i
+    L.mickey_server_set_chunk.argtypes = [vp, u64]
+    L.mickey_server_set_chunk.restype = i
+    L.mickey_server_poll_chunks.argtypes = [vp, vp, sz]
+    L.mickey_server_poll_chunks.restype = ctypes.c_int64
+    L.mickey_server_release_chunks.argtypes = [vp, vp, sz]
+    L.mickey_server_release_chunks.restype = i
+    L.mickey_server_copy_chunk.argtypes = [vp, u64, vp, u64]
+    L.mickey_server_copy_chunk.restype = i
     _lib = L
     return L
 
@@ -409,9 +419,36 @@ class Server:
         """(arrival, admission, completion) in ns of the steady clock; raises MickeyError
         with code ERANGE for a request refused at the 2^40-bit limit."""
         t = (ctypes.c_uint64 * 3)()
-        p = ctypes.c_void_p()
-        _check(load_library().mickey_server_result(self._h, int(rid), ctypes.byref(p), t))
+        _check(load_library().mickey_server_result(self._h, int(rid), None, t))
         return int(t[0]), int(t[1]), int(t[2])
+
+    # -- chunked delivery
+    CHUNK_DTYPE = [("request", "<u8"), ("handle", "<u8"), ("offset", "<u8"), ("words", "<u8"), ("out", "<u8"),
+                   ("last", "<u8")]
+
+    def set_chunk(self, chunk_bytes: int) -> None:
+        """Deliver later submissions in chunks of chunk_bytes (0: whole requests)."""
+        _check(load_library().mickey_server_set_chunk(self._h, int(chunk_bytes)))
+
+    def poll_chunks(self, cap: int = 1 << 20):
+        """Chunks finished since the last call: numpy structured array with fields
+        request, handle, offset (first word in the request's stream), words, out (device
+        address) and last."""
+        import numpy as np
+        buf = np.empty(cap, dtype=self.CHUNK_DTYPE)
+        k = load_library().mickey_server_poll_chunks(self._h, buf.ctypes.data, cap)
+        if k < 0:
+            _check(int(k))
+        return buf[:k].copy()
+
+    def release_chunks(self, handles) -> None:
+        import numpy as np
+        a = np.ascontiguousarray(handles, dtype=np.uint64)
+        _check(load_library().mickey_server_release_chunks(self._h, a.ctypes.data, len(a)))
+
+    def copy_chunk(self, handle: int, dst, nwords: int) -> None:
+        _check(load_library().mickey_server_copy_chunk(self._h, int(handle), _dev_ptr(dst, "dst", 4 * nwords),
+                                                       int(nwords)))
 
     def copy(self, rid: int, dst, nwords: int) -> None:
         _check(load_library().mickey_server_copy(self._h, int(rid), _dev_ptr(dst, "dst", 4 * nwords), int(nwords)))

@@ -51,3 +51,21 @@ def test_null_state_is_rejected_without_gpu(lib):
     assert lib.mickey_set_word_bits(None, 32) == mickey.EINVAL
     assert lib.mickey_num_instances(None) == 0
     lib.mickey_free(None)  # NULL-safe
+
+
+def test_chunk_record_layout_matches_binding(tmp_path):
+    """The binding reads mickey_chunk records as a numpy structured array: the C struct
+    must have the same field offsets and size (compiled here with the host C compiler)."""
+    import numpy as np
+    import subprocess
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "mickey.h"\n'
+                   "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(mickey_chunk),"
+                   " offsetof(mickey_chunk, request), offsetof(mickey_chunk, handle), offsetof(mickey_chunk, offset),"
+                   " offsetof(mickey_chunk, words), offsetof(mickey_chunk, out), offsetof(mickey_chunk, last));"
+                   "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    dt = np.dtype(mickey.Server.CHUNK_DTYPE)
+    assert got == [dt.itemsize] + [dt.fields[f][1] for f in dt.names]

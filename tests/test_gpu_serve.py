@@ -150,3 +150,99 @@ def test_submit_errors_and_2p40_limit():
         srv.times(over)
     assert e.value.code == mickey.ERANGE
     srv.close()
+
+
+def test_chunked_delivery_continues_states_exactly():
+    keys, ivs, ivb, init = make_pool(7, 120)
+    # budget 4 KiB: far smaller than several requests below, which stream through it
+    srv = mickey.Server(init, nslices=64, quantum_clocks=64, budget_bytes=4096)
+    init.close()
+    rng = np.random.default_rng(8)
+    plan = []  # (state, bits, chunk bytes)
+    for k in range(150):
+        chunk = int(rng.choice([0, 96, 1024]))
+        nb = 32 * int(rng.integers(1, 1024 if chunk else 64))
+        plan.append((int(rng.integers(0, 120)), nb, chunk))
+    plan[:5] = [(3, 32 * 3000, 96), (3, 64, 0), (3, 32 * 2500, 1024), (4, 32 * 8000, 96), (3, 32, 96)]
+    ids = []
+    for sid, nb, chunk in plan:
+        srv.set_chunk(chunk)
+        ids.append(srv.submit(sid, nb))
+    got = {}
+    done = []
+    whole = {}
+    for _ in range(200000):
+        srv.step()
+        ch = srv.poll_chunks()
+        for c in ch:
+            buf = torch.empty(int(c["words"]), dtype=torch.int32, device="cuda")
+            srv.copy_chunk(int(c["handle"]), buf, int(c["words"]))
+            got.setdefault(int(c["request"]), []).append(
+                (int(c["offset"]), int(c["last"]), buf.cpu().numpy().view(np.uint32)))
+        if len(ch):
+            srv.release_chunks(ch["handle"])
+        for rid in srv.poll().tolist():
+            done.append(rid)
+            sid, nb, chunk = plan[rid]
+            if not chunk:
+                whole[rid] = fetch(srv, rid, nb)
+                srv.release(rid)
+        st = srv.stats()
+        if st["waiting"] == 0 and st["running"] == 0 and not len(ch):
+            break
+    assert sorted(done) == sorted(ids)
+    assert srv.stats()["free_budget_words"] == 1024  # everything given back
+    hist = {}
+    for rid, (sid, nb, chunk) in zip(ids, plan):
+        hist.setdefault(sid, []).append((rid, nb, chunk))
+    for sid in [3, 4] + sorted(hist)[:40]:
+        reqs = hist[sid]
+        want = oracle_history(keys, ivs, ivb, sid, [nb for _, nb, _ in reqs])
+        for (rid, nb, chunk), w in zip(reqs, want):
+            if not chunk:
+                assert rid not in got
+                assert (whole[rid] == w).all(), (sid, rid)
+                continue
+            parts = sorted(got[rid], key=lambda t: t[0])
+            sizes = [len(p[2]) for p in parts]
+            assert all(z == chunk // 4 for z in sizes[:-1]) and 0 < sizes[-1] <= chunk // 4, (rid, sizes)
+            assert [p[0] for p in parts] == list(np.cumsum([0] + sizes[:-1])), rid
+            assert [p[1] for p in parts] == [0] * (len(parts) - 1) + [1], rid
+            assert (np.concatenate([p[2] for p in parts]) == w).all(), (sid, rid)
+        assert srv.state_bits(sid) == sum(nb for _, nb, _ in reqs)
+    # per-state order across whole and chunked requests on state 3
+    t = [srv.times(r)[2] for r, _, _ in hist[3]]
+    assert t == sorted(t)
+    srv.close()
+
+
+def test_chunked_delivery_errors():
+    keys, ivs, ivb, init = make_pool(9, 4, mixed=False)
+    srv = mickey.Server(init, nslices=64, quantum_clocks=32, budget_bytes=1024)
+    init.close()
+    with pytest.raises(mickey.MickeyError):
+        srv.set_chunk(6)  # not whole words
+    with pytest.raises(mickey.MickeyError):
+        srv.set_chunk(2048)  # larger than the budget
+    with pytest.raises(mickey.MickeyError):
+        srv.submit(0, 32 * 1024)  # whole delivery: larger than the budget
+    srv.set_chunk(256)
+    rid = srv.submit(0, 32 * 1024)  # 4 KiB through a 1 KiB budget
+    seen = []
+    for _ in range(10000):
+        srv.step()
+        ch = srv.poll_chunks()
+        seen += ch.tolist()
+        if len(ch):
+            srv.release_chunks(ch["handle"])
+            with pytest.raises(mickey.MickeyError):
+                srv.release_chunks(ch["handle"][:1])  # already given back
+        if srv.poll().tolist() == [rid]:
+            break
+    assert len(seen) == 16
+    with pytest.raises(mickey.MickeyError):
+        srv.release(rid)  # chunked requests are released chunk by chunk
+    with pytest.raises(mickey.MickeyError):
+        srv.copy(rid, torch.empty(8, dtype=torch.int32, device="cuda"), 8)
+    assert srv.times(rid)[2] > 0
+    srv.close()
