@@ -103,6 +103,44 @@ def bench_rowmajor(torch, mickey, synth, reps: int = 3):
             "waves": n // 32 // 64, "note": "2^20 instances fill 512 of 2048 wave slots at 32 instances per lane"}
 
 
+def bench_grain(torch, mickey, synth, reps: int = 5):
+    """Bitsliced Grain v1: 2^22 instances (splitmix64 seed 6 keys and 64-bit IVs), 8192
+    bits each into bit-planes (4 GiB), init and generate timed separately.  At 36 VALU
+    ops per clock for 32 instances the kernel writes faster than it computes, so its
+    roofline is the HBM write bandwidth."""
+    seed, n, nbits, _ = synth.workload("grain-4m")
+    keys, ivs = synth.grain_keys_ivs(seed, n)
+    dk, dv = torch.from_numpy(keys).cuda(), torch.from_numpy(ivs).cuda()
+    stream = torch.cuda.current_stream()
+    g = mickey.Grain(dk, dv, stream=stream)
+    out = torch.empty(nbits * g.pitch, dtype=torch.uint8, device="cuda")
+    g.generate(nbits, mickey.BITSLICED, out)  # warm-up
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_init, t_gen = [], []
+    for _ in range(reps):
+        ev[0].record(stream)
+        g.rekey(dk, dv)
+        ev[1].record(stream)
+        g.generate(nbits, mickey.BITSLICED, out)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        t_init.append(ev[0].elapsed_time(ev[1]))
+        t_gen.append(ev[1].elapsed_time(ev[2]))
+    g.close()
+    ti, tg = float(np.mean(t_init)), float(np.mean(t_gen))
+    bits = n * nbits
+    ops = mickey.grain_ops_per_clock() * (n // 32) * nbits
+    wbytes = bits / 8 + 2 * 20 * n  # keystream planes, plus the 160 state planes read and written
+    print("# grain-4m: init %.3f ms, generate %.3f ms" % (ti, tg), file=sys.stderr, flush=True)
+    return {"workload": "grain-4m: 2^22 Grain v1 instances, 80-bit keys, 64-bit IVs (splitmix64 seed 6), "
+                        "8192 bits each, bitsliced planes",
+            "gbit_s": round(bits / ((ti + tg) * 1e-3) / 1e9, 3), "init_ms": round(ti, 4),
+            "generate_ms": round(tg, 4), "generate_gbit_s": round(bits / (tg * 1e-3) / 1e9, 3),
+            "hbm_gb_s": round(wbytes / (tg * 1e-3) / 1e9, 1), "hbm_frac": round(wbytes / (tg * 1e-3) / 8e12, 4),
+            "valu_frac": round(ops / (tg * 1e-3) / 78.6432e12, 4),
+            "ops_per_clock_per_32": mickey.grain_ops_per_clock()}
+
+
 def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 12):
     """10,000 fresh requests (seed 4): IV lengths 0..80, lengths log-uniform in
     [2^8, 2^24) bits; one persistent work-queue launch replayed from a HIP graph,
@@ -373,6 +411,7 @@ def main() -> int:
     ap.add_argument("--no-rowmajor", action="store_true", help="skip the row-major 2^20 x 65536 measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 10,000-request batched measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the served measurements")
+    ap.add_argument("--no-grain", action="store_true", help="skip the bitsliced Grain leg")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="Poisson arrival window of the served run")
     ap.add_argument("--serve-max-kib", type=int, default=64 << 10, help="largest served request (KiB)")
     ap.add_argument("--serve-drain", type=float, default=30.0,
@@ -515,6 +554,8 @@ def main() -> int:
     torch.cuda.empty_cache()
     if not args.no_rowmajor:
         res["rowmajor_1m"] = bench_rowmajor(torch, mickey, synth)
+    if not args.no_grain:
+        res["grain_4m"] = bench_grain(torch, mickey, synth)
     if not args.no_batch:
         res["batch_10k"] = bench_batch(torch, mickey, synth)
     if not args.no_serve:

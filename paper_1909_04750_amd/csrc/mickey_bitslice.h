@@ -21,6 +21,8 @@
 // non-linear register with complement masks COMP0/COMP1 and control-selected feedback
 // masks FB0/FB1; each register's control bit comes from the other register.
 #pragma once
+#include "bitmatrix.h"
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <utility>
@@ -59,8 +61,9 @@ constexpr bool in_set(const uint8_t (&set)[N], int i)
 template <size_t N>
 constexpr int set_size(const uint8_t (&)[N]) { return (int)N; }
 
-// bitop3 truth-table operands: result bit = imm[(a << 2) | (b << 1) | c].
-constexpr int TA = 0xF0, TB = 0xCC, TC = 0xAA;
+using bitops::TA;
+using bitops::TB;
+using bitops::TC;
 
 // Algorithmic VALU ops per clock per word (see the table at the top).
 constexpr int ops_per_clock()

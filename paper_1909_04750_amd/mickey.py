@@ -1,4 +1,4 @@
-"""ctypes binding of libmickey.so (include/mickey.h).  Argument marshalling only: every
+"""ctypes binding of libmickey.so (include/mickey.h, include/grain.h).  Argument marshalling only: every
 step of the keystream path runs in the library's HIP kernels; torch supplies device
 memory and the current stream.  There is no fallback: if the library is not built, or
 there is no GPU, calls raise."""
@@ -28,7 +28,11 @@ EXPORTED = [
     "mickey_server_release_many", "mickey_server_times_many", "mickey_server_wait",
     "mickey_server_set_chunk", "mickey_server_poll_chunks", "mickey_server_release_chunks",
     "mickey_server_copy_chunk",
+    "grain_init", "grain_rekey", "grain_generate", "grain_generate_rowmajor", "grain_free", "grain_set_stream",
+    "grain_num_instances", "grain_bits_generated", "grain_plane_pitch", "grain_state_export",
+    "grain_state_import", "grain_sync", "grain_ops_per_clock",
 ]
+GRAIN_PACKED_STATE_BYTES = 20
 
 _lib = None
 
@@ -141,6 +145,32 @@ def load_library():
     L.mickey_server_release_chunks.restype = i
     L.mickey_server_copy_chunk.argtypes = [vp, u64, vp, u64]
     L.mickey_server_copy_chunk.restype = i
+    L.grain_init.argtypes = [vp, vp, sz, vp]
+    L.grain_init.restype = vp
+    L.grain_rekey.argtypes = [vp, vp, vp]
+    L.grain_rekey.restype = i
+    L.grain_generate.argtypes = [vp, u64, vp, i]
+    L.grain_generate.restype = i
+    L.grain_generate_rowmajor.argtypes = [vp, u64, vp, vp]
+    L.grain_generate_rowmajor.restype = i
+    L.grain_free.argtypes = [vp]
+    L.grain_free.restype = None
+    L.grain_set_stream.argtypes = [vp, vp]
+    L.grain_set_stream.restype = i
+    L.grain_num_instances.argtypes = [vp]
+    L.grain_num_instances.restype = sz
+    L.grain_bits_generated.argtypes = [vp]
+    L.grain_bits_generated.restype = u64
+    L.grain_plane_pitch.argtypes = [sz]
+    L.grain_plane_pitch.restype = sz
+    L.grain_state_export.argtypes = [vp, vp, ctypes.POINTER(u64)]
+    L.grain_state_export.restype = i
+    L.grain_state_import.argtypes = [vp, vp, u64]
+    L.grain_state_import.restype = i
+    L.grain_sync.argtypes = [vp]
+    L.grain_sync.restype = i
+    L.grain_ops_per_clock.argtypes = []
+    L.grain_ops_per_clock.restype = i
     _lib = L
     return L
 
@@ -469,6 +499,95 @@ class Server:
     def close(self) -> None:
         if getattr(self, "_h", None):
             load_library().mickey_server_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def grain_ops_per_clock() -> int:
+    return int(load_library().grain_ops_per_clock())
+
+
+class Grain:
+    """n bitsliced Grain (v1) instances resident on the GPU (grain_state): 80-bit keys
+    (n x 10 bytes) and 64-bit IVs (n x 8 bytes), bits least significant first."""
+
+    def __init__(self, keys, ivs, stream=None):
+        n = int(keys.shape[0])
+        L = load_library()
+        h = L.grain_init(_dev_ptr(keys, "keys", 10 * n), _dev_ptr(ivs, "ivs", 8 * n), n, _stream_handle(stream))
+        if not h:
+            raise MickeyError(L.mickey_last_error(), L.mickey_last_error_message().decode())
+        self._h = ctypes.c_void_p(h)
+        self.n = n
+
+    def rekey(self, keys, ivs) -> None:
+        _check(load_library().grain_rekey(self._h, _dev_ptr(keys, "keys", 10 * self.n),
+                                          _dev_ptr(ivs, "ivs", 8 * self.n)))
+
+    @property
+    def bits_generated(self) -> int:
+        return int(load_library().grain_bits_generated(self._h))
+
+    @property
+    def pitch(self) -> int:
+        return int(load_library().grain_plane_pitch(self.n))
+
+    def set_stream(self, stream) -> None:
+        _check(load_library().grain_set_stream(self._h, _stream_handle(stream)))
+
+    def generate(self, nbits: int, layout: int = BITSLICED, out=None):
+        import torch
+        nbits = int(nbits)
+        if layout == BITSLICED:
+            nbytes = nbits * self.pitch
+            if out is None:
+                out = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        elif layout in (ROWMAJOR_U32, ROWMAJOR_F32):
+            nbytes = self.n * (nbits // 32) * 4
+            if out is None:
+                dt = torch.int32 if layout == ROWMAJOR_U32 else torch.float32
+                out = torch.empty((self.n, nbits // 32), dtype=dt, device="cuda")
+        else:
+            raise ValueError("unknown layout %r" % layout)
+        _check(load_library().grain_generate(self._h, nbits, _dev_ptr(out, "out", nbytes), int(layout)))
+        return out
+
+    def generate_rowmajor(self, nbits: int, out_u32=None, out_f32=None, want_u32=True, want_f32=True):
+        import torch
+        nbits = int(nbits)
+        if want_u32 and out_u32 is None:
+            out_u32 = torch.empty((self.n, nbits // 32), dtype=torch.int32, device="cuda")
+        if want_f32 and out_f32 is None:
+            out_f32 = torch.empty((self.n, nbits // 32), dtype=torch.float32, device="cuda")
+        nbytes = self.n * (nbits // 32) * 4
+        pu = None if out_u32 is None else _dev_ptr(out_u32, "out_u32", nbytes)
+        pf = None if out_f32 is None else _dev_ptr(out_f32, "out_f32", nbytes)
+        _check(load_library().grain_generate_rowmajor(self._h, nbits, pu, pf))
+        return out_u32, out_f32
+
+    def export_state(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.n, GRAIN_PACKED_STATE_BYTES), dtype=torch.uint8, device="cuda")
+        bits = ctypes.c_uint64(0)
+        _check(load_library().grain_state_export(self._h, _dev_ptr(out, "packed", 20 * self.n), ctypes.byref(bits)))
+        return out, int(bits.value)
+
+    def import_state(self, packed, bits_generated: int) -> None:
+        _check(load_library().grain_state_import(self._h, _dev_ptr(packed, "packed", 20 * self.n),
+                                                 int(bits_generated)))
+
+    def sync(self) -> None:
+        _check(load_library().grain_sync(self._h))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load_library().grain_free(self._h)
             self._h = None
 
     def __del__(self):

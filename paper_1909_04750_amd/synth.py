@@ -57,6 +57,16 @@ def keys_ivs(seed: int, n: int, idx=None):
     return keys, ivs
 
 
+def grain_keys_ivs(seed: int, n: int, idx=None):
+    """Grain inputs: keys uint8 [k, 10] as keys_ivs, IVs uint8 [k, 8] = draw(4i+2)
+    big-endian (the 64-bit IV)."""
+    i = np.arange(n, dtype=np.uint64) if idx is None else np.asarray(idx, dtype=np.uint64)
+    keys, _ = keys_ivs(seed, n, idx)
+    x = draws(seed, np.uint64(4) * i + np.uint64(2))
+    ivs = x.astype(">u8").view(np.uint8).reshape(-1, 8).copy()
+    return keys, ivs
+
+
 def iv_lengths_mixed(seed: int, n: int, idx=None) -> np.ndarray:
     """IV lengths uniform in {0, 32, 64, 80} bits (uint8 [k])."""
     i = np.arange(n, dtype=np.uint64) if idx is None else np.asarray(idx, dtype=np.uint64)
@@ -118,6 +128,8 @@ def workload(name: str):
         "rowmajor-1m": (3, 1 << 20, 65536, "mixed"),
         # 10,000 fresh requests, IV lengths 0..80, lengths log-uniform in [2^8, 2^24) bits
         "batch-10k": (4, 10000, None, "batch"),
+        # Grain: 2^22 instances, 80-bit keys, 64-bit IVs, 8192 bits each, bitsliced
+        "grain-4m": (6, 1 << 22, 8192, "grain"),
     }
     return table[name]
 

@@ -9,13 +9,14 @@ import pytest
 from paper_1909_04750_amd import build, mickey
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "mickey.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("mickey.h", "grain.h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"\b(mickey_\w+)\s*\(", text)
+    names = []
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names += re.findall(r"\b((?:mickey|grain)_\w+)\s*\(", text)
     return sorted(set(names))
 
 
@@ -42,6 +43,8 @@ def test_host_only_queries(lib):
     assert mickey.plane_pitch(65) == 16
     assert mickey.plane_pitch(1 << 22) == (1 << 22) // 8
     assert mickey.ops_per_clock() == 328
+    assert mickey.grain_ops_per_clock() == 36
+    assert lib.grain_plane_pitch(65) == 16
 
 
 def test_null_state_is_rejected_without_gpu(lib):
@@ -51,6 +54,11 @@ def test_null_state_is_rejected_without_gpu(lib):
     assert lib.mickey_set_word_bits(None, 32) == mickey.EINVAL
     assert lib.mickey_num_instances(None) == 0
     lib.mickey_free(None)  # NULL-safe
+    assert lib.grain_generate(None, 32, None, 0) == mickey.EINVAL
+    assert lib.grain_init(None, None, 4, None) is None
+    assert lib.mickey_last_error() == mickey.EINVAL
+    assert lib.grain_num_instances(None) == 0
+    lib.grain_free(None)
 
 
 def test_chunk_record_layout_matches_binding(tmp_path):
