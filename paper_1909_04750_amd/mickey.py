@@ -1,4 +1,4 @@
-"""ctypes binding of libmickey.so (include/mickey.h, include/grain.h).  Argument marshalling only: every
+"""ctypes binding of libmickey.so (include/mickey.h, include/grain.h, include/aes.h).  Argument marshalling only: every
 step of the keystream path runs in the library's HIP kernels; torch supplies device
 memory and the current stream.  There is no fallback: if the library is not built, or
 there is no GPU, calls raise."""
@@ -31,6 +31,9 @@ EXPORTED = [
     "grain_init", "grain_rekey", "grain_generate", "grain_generate_rowmajor", "grain_free", "grain_set_stream",
     "grain_num_instances", "grain_bits_generated", "grain_plane_pitch", "grain_state_export",
     "grain_state_import", "grain_sync", "grain_ops_per_clock",
+    "aes_ctr_init", "aes_ctr_generate", "aes_ctr_generate_rowmajor", "aes_ctr_seek", "aes_ctr_free",
+    "aes_ctr_set_stream", "aes_ctr_num_instances", "aes_ctr_bits_generated", "aes_ctr_plane_pitch",
+    "aes_ctr_sync", "aes_ctr_ops_per_block",
 ]
 GRAIN_PACKED_STATE_BYTES = 20
 
@@ -171,6 +174,28 @@ def load_library():
     L.grain_sync.restype = i
     L.grain_ops_per_clock.argtypes = []
     L.grain_ops_per_clock.restype = i
+    L.aes_ctr_init.argtypes = [vp, vp, sz, vp]
+    L.aes_ctr_init.restype = vp
+    L.aes_ctr_generate.argtypes = [vp, u64, vp, i]
+    L.aes_ctr_generate.restype = i
+    L.aes_ctr_generate_rowmajor.argtypes = [vp, u64, vp, vp]
+    L.aes_ctr_generate_rowmajor.restype = i
+    L.aes_ctr_seek.argtypes = [vp, u64]
+    L.aes_ctr_seek.restype = i
+    L.aes_ctr_free.argtypes = [vp]
+    L.aes_ctr_free.restype = None
+    L.aes_ctr_set_stream.argtypes = [vp, vp]
+    L.aes_ctr_set_stream.restype = i
+    L.aes_ctr_num_instances.argtypes = [vp]
+    L.aes_ctr_num_instances.restype = sz
+    L.aes_ctr_bits_generated.argtypes = [vp]
+    L.aes_ctr_bits_generated.restype = u64
+    L.aes_ctr_plane_pitch.argtypes = [sz]
+    L.aes_ctr_plane_pitch.restype = sz
+    L.aes_ctr_sync.argtypes = [vp]
+    L.aes_ctr_sync.restype = i
+    L.aes_ctr_ops_per_block.argtypes = []
+    L.aes_ctr_ops_per_block.restype = i
     _lib = L
     return L
 
@@ -588,6 +613,82 @@ class Grain:
     def close(self) -> None:
         if getattr(self, "_h", None):
             load_library().grain_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def aes_ops_per_block() -> int:
+    return int(load_library().aes_ctr_ops_per_block())
+
+
+class AesCtr:
+    """n AES-128 counter-mode streams under one key (aes_ctr_state): stream i's block j is
+    AES_K(nonce_i || j as 64-bit big-endian).  key: 16 bytes, nonces: n x 8 bytes (device)."""
+
+    def __init__(self, key, nonces, stream=None):
+        n = int(nonces.shape[0])
+        L = load_library()
+        h = L.aes_ctr_init(_dev_ptr(key, "key", 16), _dev_ptr(nonces, "nonces", 8 * n), n, _stream_handle(stream))
+        if not h:
+            raise MickeyError(L.mickey_last_error(), L.mickey_last_error_message().decode())
+        self._h = ctypes.c_void_p(h)
+        self.n = n
+
+    @property
+    def bits_generated(self) -> int:
+        return int(load_library().aes_ctr_bits_generated(self._h))
+
+    @property
+    def pitch(self) -> int:
+        return int(load_library().aes_ctr_plane_pitch(self.n))
+
+    def seek(self, block: int) -> None:
+        _check(load_library().aes_ctr_seek(self._h, int(block)))
+
+    def set_stream(self, stream) -> None:
+        _check(load_library().aes_ctr_set_stream(self._h, _stream_handle(stream)))
+
+    def generate(self, nbits: int, layout: int = BITSLICED, out=None):
+        import torch
+        nbits = int(nbits)
+        if layout == BITSLICED:
+            nbytes = nbits * self.pitch
+            if out is None:
+                out = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        elif layout in (ROWMAJOR_U32, ROWMAJOR_F32):
+            nbytes = self.n * (nbits // 32) * 4
+            if out is None:
+                dt = torch.int32 if layout == ROWMAJOR_U32 else torch.float32
+                out = torch.empty((self.n, nbits // 32), dtype=dt, device="cuda")
+        else:
+            raise ValueError("unknown layout %r" % layout)
+        _check(load_library().aes_ctr_generate(self._h, nbits, _dev_ptr(out, "out", nbytes), int(layout)))
+        return out
+
+    def generate_rowmajor(self, nbits: int, out_u32=None, out_f32=None, want_u32=True, want_f32=True):
+        import torch
+        nbits = int(nbits)
+        if want_u32 and out_u32 is None:
+            out_u32 = torch.empty((self.n, nbits // 32), dtype=torch.int32, device="cuda")
+        if want_f32 and out_f32 is None:
+            out_f32 = torch.empty((self.n, nbits // 32), dtype=torch.float32, device="cuda")
+        nbytes = self.n * (nbits // 32) * 4
+        pu = None if out_u32 is None else _dev_ptr(out_u32, "out_u32", nbytes)
+        pf = None if out_f32 is None else _dev_ptr(out_f32, "out_f32", nbytes)
+        _check(load_library().aes_ctr_generate_rowmajor(self._h, nbits, pu, pf))
+        return out_u32, out_f32
+
+    def sync(self) -> None:
+        _check(load_library().aes_ctr_sync(self._h))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load_library().aes_ctr_free(self._h)
             self._h = None
 
     def __del__(self):

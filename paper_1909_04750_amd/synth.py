@@ -67,6 +67,16 @@ def grain_keys_ivs(seed: int, n: int, idx=None):
     return keys, ivs
 
 
+def aes_inputs(seed: int, n: int, idx=None):
+    """AES-CTR inputs: the 16-byte key = draws 4n and 4n+1 big-endian (uint8 [16]), and
+    nonce i = draw 4i big-endian (uint8 [k, 8])."""
+    i = np.arange(n, dtype=np.uint64) if idx is None else np.asarray(idx, dtype=np.uint64)
+    kd = draws(seed, np.array([4 * n, 4 * n + 1], dtype=np.uint64))
+    key = kd.astype(">u8").view(np.uint8).reshape(16).copy()
+    nonces = draws(seed, np.uint64(4) * i).astype(">u8").view(np.uint8).reshape(-1, 8).copy()
+    return key, nonces
+
+
 def iv_lengths_mixed(seed: int, n: int, idx=None) -> np.ndarray:
     """IV lengths uniform in {0, 32, 64, 80} bits (uint8 [k])."""
     i = np.arange(n, dtype=np.uint64) if idx is None else np.asarray(idx, dtype=np.uint64)
@@ -130,6 +140,8 @@ def workload(name: str):
         "batch-10k": (4, 10000, None, "batch"),
         # Grain: 2^22 instances, 80-bit keys, 64-bit IVs, 8192 bits each, bitsliced
         "grain-4m": (6, 1 << 22, 8192, "grain"),
+        # AES-128-CTR: one key, 2^22 streams with 64-bit nonces, 8192 bits (64 blocks) each
+        "aes-4m": (7, 1 << 22, 8192, "aes"),
     }
     return table[name]
 

@@ -9,14 +9,14 @@ import pytest
 from paper_1909_04750_amd import build, mickey
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("mickey.h", "grain.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("mickey.h", "grain.h", "aes.h")]
 
 
 def declared_functions():
     names = []
     for h in HEADERS:
         text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
-        names += re.findall(r"\b((?:mickey|grain)_\w+)\s*\(", text)
+        names += re.findall(r"\b((?:mickey|grain|aes_ctr)_\w+)\s*\(", text)
     return sorted(set(names))
 
 
@@ -45,6 +45,8 @@ def test_host_only_queries(lib):
     assert mickey.ops_per_clock() == 328
     assert mickey.grain_ops_per_clock() == 36
     assert lib.grain_plane_pitch(65) == 16
+    assert lib.aes_ctr_plane_pitch(65) == 16
+    assert mickey.aes_ops_per_block() == 9 * 16 * 94 + 9 * 4 * 96 + 80
 
 
 def test_null_state_is_rejected_without_gpu(lib):
@@ -59,6 +61,9 @@ def test_null_state_is_rejected_without_gpu(lib):
     assert lib.mickey_last_error() == mickey.EINVAL
     assert lib.grain_num_instances(None) == 0
     lib.grain_free(None)
+    assert lib.aes_ctr_generate(None, 128, None, 0) == mickey.EINVAL
+    assert lib.aes_ctr_init(None, None, 4, None) is None
+    lib.aes_ctr_free(None)
 
 
 def test_chunk_record_layout_matches_binding(tmp_path):
