@@ -141,6 +141,39 @@ def bench_grain(torch, mickey, synth, reps: int = 5):
             "ops_per_clock_per_32": mickey.grain_ops_per_clock()}
 
 
+def bench_aes(torch, mickey, synth, reps: int = 3):
+    """Bitsliced AES-128-CTR: one key, 2^22 streams (splitmix64 seed 7 key and 64-bit
+    nonces), 8192 bits (64 blocks) each into bit-planes (4 GiB).  VALU-bound: about 4.2
+    lane-ops per keystream bit, mostly the S-box circuit."""
+    seed, n, nbits, _ = synth.workload("aes-4m")
+    key, nonces = synth.aes_inputs(seed, n)
+    dk, dn = torch.from_numpy(key).cuda(), torch.from_numpy(nonces).cuda()
+    stream = torch.cuda.current_stream()
+    a = mickey.AesCtr(dk, dn, stream=stream)
+    out = torch.empty(nbits * a.pitch, dtype=torch.uint8, device="cuda")
+    a.generate(nbits, mickey.BITSLICED, out)  # warm-up
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t_gen = []
+    for _ in range(reps):
+        a.seek(0)
+        ev[0].record(stream)
+        a.generate(nbits, mickey.BITSLICED, out)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        t_gen.append(ev[0].elapsed_time(ev[1]))
+    a.close()
+    tg = float(np.mean(t_gen))
+    bits = n * nbits
+    ops = mickey.aes_ops_per_block() * (n // 32) * (nbits // 128)
+    print("# aes-4m: generate %.3f ms" % tg, file=sys.stderr, flush=True)
+    return {"workload": "aes-4m: AES-128-CTR, one key, 2^22 streams with 64-bit nonces (splitmix64 seed 7), "
+                        "8192 bits (64 blocks) each, bitsliced planes",
+            "generate_ms": round(tg, 4), "generate_gbit_s": round(bits / (tg * 1e-3) / 1e9, 3),
+            "valu_frac": round(ops / (tg * 1e-3) / 78.6432e12, 4),
+            "ops_per_block_per_32": mickey.aes_ops_per_block(),
+            "hbm_frac": round(bits / 8 / (tg * 1e-3) / 8e12, 4)}
+
+
 def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 12):
     """10,000 fresh requests (seed 4): IV lengths 0..80, lengths log-uniform in
     [2^8, 2^24) bits; one persistent work-queue launch replayed from a HIP graph,
@@ -412,6 +445,7 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the 10,000-request batched measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the served measurements")
     ap.add_argument("--no-grain", action="store_true", help="skip the bitsliced Grain leg")
+    ap.add_argument("--no-aes", action="store_true", help="skip the bitsliced AES-CTR leg")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="Poisson arrival window of the served run")
     ap.add_argument("--serve-max-kib", type=int, default=64 << 10, help="largest served request (KiB)")
     ap.add_argument("--serve-drain", type=float, default=30.0,
@@ -556,6 +590,8 @@ def main() -> int:
         res["rowmajor_1m"] = bench_rowmajor(torch, mickey, synth)
     if not args.no_grain:
         res["grain_4m"] = bench_grain(torch, mickey, synth)
+    if not args.no_aes:
+        res["aes_4m"] = bench_aes(torch, mickey, synth)
     if not args.no_batch:
         res["batch_10k"] = bench_batch(torch, mickey, synth)
     if not args.no_serve:
