@@ -60,7 +60,9 @@ int aes_ctr_generate(aes_ctr_state *st, uint64_t nbits, void *out, int layout);
 /* Row-major delivery to u32 words, f32 values, or both (either may be NULL). */
 int aes_ctr_generate_rowmajor(aes_ctr_state *st, uint64_t nbits, uint32_t *out_u32, float *out_f32);
 
-/* Move every stream to block `block` (the next block generated). */
+/* Move every stream to block `block` (the next block generated).  Blocks 0 .. 2^64 - 2
+ * can be generated: a call that would move the counter to 2^64 - 1 or beyond fails with
+ * MICKEY_ERANGE. */
 int aes_ctr_seek(aes_ctr_state *st, uint64_t block);
 
 void aes_ctr_free(aes_ctr_state *st); /* NULL-safe; waits for the state's stream */

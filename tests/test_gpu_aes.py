@@ -52,7 +52,7 @@ def test_standard_vectors_through_the_counter_layout():
     f = blocks[1]
     nonces = np.zeros((40, 8), dtype=np.uint8)
     nonces[5] = np.frombuffer(f["in"][:8], dtype=np.uint8)
-    a = mickey.AesCtr(to_dev(np.frombuffer(f["key"], dtype=np.uint8)), to_dev(nonces))
+    a = mickey.AesCtr(to_dev(np.frombuffer(f["key"], dtype=np.uint8).copy()), to_dev(nonces))
     a.seek(int.from_bytes(f["in"][8:], "big"))
     bits = planes_to_bits(a.generate(128), 128, a.pitch, 40)
     assert np.packbits(bits[5]).tobytes() == f["out"]
@@ -60,7 +60,7 @@ def test_standard_vectors_through_the_counter_layout():
     # SP 800-38A F.5.1: four consecutive counter blocks from f0f1...fe ff
     c = ctrs[0]
     nonces = np.tile(np.frombuffer(c["t1"][:8], dtype=np.uint8), (3, 1))
-    a = mickey.AesCtr(to_dev(np.frombuffer(c["key"], dtype=np.uint8)), to_dev(nonces))
+    a = mickey.AesCtr(to_dev(np.frombuffer(c["key"], dtype=np.uint8).copy()), to_dev(nonces))
     a.seek(int.from_bytes(c["t1"][8:], "big"))
     u = a.generate(512, mickey.ROWMAJOR_U32)
     got = u.cpu().numpy().view(np.uint32).astype(">u4").tobytes()[:64]
@@ -84,10 +84,10 @@ def test_continuation_and_seek():
     a = mickey.AesCtr(to_dev(key), to_dev(nonces))
     parts = [planes_to_bits(a.generate(128 * k), 128 * k, a.pitch, n) for k in (1, 2)]
     assert (np.concatenate(parts, axis=1) == oracle_bits(key, nonces, 0, 3)).all()
-    a.seek((1 << 64) - 2)  # the counter's last two blocks
-    assert (planes_to_bits(a.generate(256), 256, a.pitch, n) == oracle_bits(key, nonces, (1 << 64) - 2, 2)).all()
+    a.seek((1 << 64) - 3)  # the counter's last two usable blocks (it must stay below 2^64 - 1)
+    assert (planes_to_bits(a.generate(256), 256, a.pitch, n) == oracle_bits(key, nonces, (1 << 64) - 3, 2)).all()
     with pytest.raises(mickey.MickeyError) as e:
-        a.generate(128)  # would wrap the 64-bit block counter
+        a.generate(128)  # would move the 64-bit block counter to 2^64 - 1
     assert e.value.code == mickey.ERANGE
     a.close()
 
