@@ -20,7 +20,7 @@ def to_dev(a):
 
 def counter_blocks(nonces, j0):
     """Initial counter blocks nonce_i || j0 (64-bit big-endian)."""
-    low = np.frombuffer(np.uint64(j0).astype(">u8").tobytes(), dtype=np.uint8)
+    low = np.array([j0], dtype=">u8").view(np.uint8)
     return np.concatenate([nonces, np.tile(low, (nonces.shape[0], 1))], axis=1)
 
 
