@@ -115,7 +115,7 @@ def test_error_paths():
     assert a.bits_generated == 0
     big = torch.zeros(8 * 8 + 4, dtype=torch.uint8, device=DEV)
     with pytest.raises(mickey.MickeyError):
-        mickey.AesCtr(to_dev(key), big[4:])  # nonces not 8-byte aligned
+        mickey.AesCtr(to_dev(key), big[4:].view(8, 8))  # nonces not 8-byte aligned
     a.close()
 
 

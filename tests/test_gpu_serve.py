@@ -211,7 +211,7 @@ def test_chunked_delivery_continues_states_exactly():
             assert (np.concatenate([p[2] for p in parts]) == w).all(), (sid, rid)
         assert srv.state_bits(sid) == sum(nb for _, nb, _ in reqs)
     # per-state order across whole and chunked requests on state 3
-    t = [srv.times(r)[2] for r, _, _ in hist[3]]
+    t = srv.times_many([r for r, _, _ in hist[3]])[:, 2].tolist()
     assert t == sorted(t)
     srv.close()
 
