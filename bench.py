@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("csrc/mickey_bitslice.h", "csrc/mickey_device.h", "csrc/mickey_kernels.hip"):
+    for f in ("csrc/bitmatrix.h", "csrc/mickey_bitslice.h", "csrc/mickey_device.h", "csrc/mickey_kernels.hip"):
         h.update(open(os.path.join(ROOT, "paper_1909_04750_amd", f), "rb").read())
     return h.hexdigest()[:16]
 
