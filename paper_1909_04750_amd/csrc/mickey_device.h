@@ -169,6 +169,24 @@ __device__ __forceinline__ void st_word(char *p, const Word<K> &v)
     }
 }
 
+// One keystream word (K 32-bit words) at the lane's offset in a wave-uniform plane: a
+// vector buffer store whose resource is built from the scalar plane address, so that the
+// per-clock address arithmetic stays on the scalar unit.
+template <int K>
+__device__ __forceinline__ void store_plane(char *plane, uint32_t voff, const Word<K> &v)
+{
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(plane, (short)0, 0x7FFFFFFF, 0x00020000);
+    if constexpr (K == 1) {
+        __builtin_amdgcn_raw_buffer_store_b32(v.w[0], rs, (int)voff, 0, 0);
+    } else {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        u32x2 d;
+        d.x = v.w[0];
+        d.y = v.w[1];
+        __builtin_amdgcn_raw_buffer_store_b64(d, rs, (int)voff, 0, 0);
+    }
+}
+
 template <int K>
 __device__ __forceinline__ void load_state(Regs<K> &x, const uint32_t *state, size_t pitch, uint32_t voff)
 {

@@ -70,18 +70,18 @@ gen_bitsliced_kernel(uint32_t *__restrict__ state, uint32_t ngroups, uint32_t pi
     const uint32_t voff = g * 4u * K;
     Regs<K> x;
     load_state<K>(x, state, pitch, voff);
-    char *plane = (char *)out;
-    // count down to zero: the loop test is a scalar 64-bit compare
-    for (uint64_t it = nbits / kUnroll; it != 0; --it) {
+    char *plane = (char *)out;  // wave-uniform
+    uint64_t t = 0;
+    for (; t + kUnroll <= nbits; t += kUnroll) {
 #pragma unroll
         for (int u = 0; u < kUnroll; u++) {
-            st_word<K>(plane + voff, x.r[0] ^ x.s[0]);
+            store_plane<K>(plane, voff, x.r[0] ^ x.s[0]);
             plane += pitch;
             clock_gen<K>(x);
         }
     }
-    for (uint64_t t = nbits - nbits % kUnroll; t < nbits; t++) {
-        st_word<K>(plane + voff, x.r[0] ^ x.s[0]);
+    for (; t < nbits; t++) {
+        store_plane<K>(plane, voff, x.r[0] ^ x.s[0]);
         plane += pitch;
         clock_gen<K>(x);
     }
