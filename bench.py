@@ -254,8 +254,8 @@ def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 
 
 
 def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: float, rate: float = 20000.0,
-                nstates: int = 10 ** 6, budget: int = 64 << 30, chunk: int = 64 << 10, sat_bytes: int = 56 << 10,
-                sat_seconds: float = 3.0, nverify: int = 16):
+                nstates: int = 10 ** 6, budget: int = 64 << 30, chunk: int = 64 << 10, sat_seconds: float = 3.0,
+                nverify: int = 16):
     """Served generation over 10^6 resident states (splitmix64 seed 5 keys and 80-bit
     IVs, initialised).  Open loop: Poisson arrivals at `rate`/s for `duration` s, state
     uniform, size log-uniform in [4 KiB, max_bytes], delivered in `chunk`-byte chunks
@@ -263,8 +263,8 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
     scheduled arrival.  The run stops when every request is done or `drain` s after the
     last arrival; requests still running then are censored (their latency is only known
     to exceed the time they have waited).  Closed loop (saturation): every state keeps one
-    sat_bytes request in flight for sat_seconds; compared with the plain kernel on the
-    same 10^6 instances."""
+    request of the same size distribution in flight, chunked through the same budget, for
+    sat_seconds; compared with the plain kernel on the same 10^6 instances."""
     keys, ivs = synth.keys_ivs(5, nstates)
     dk, dv = torch.from_numpy(keys).cuda(), torch.from_numpy(ivs).cuda()
     init = mickey.Mickey(dk, dv)
@@ -372,62 +372,73 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
     }
     print("# serve open loop: %d/%d requests done, p50 %s s p99 %s s (lower bound %.1f s)" % (
         int(done.sum()), n, p50, p99, p99_lb), file=sys.stderr, flush=True)
-    # -- closed loop: every state busy
-    sat_bits = 8 * sat_bytes
+    # -- closed loop: every state always has a request in flight (saturation)
     srng = np.random.default_rng(55)
+    lo, hi = np.log2(4096), np.log2(max_bytes)
 
-    def sizes(k):  # bits, whole 32-bit words, uniform in sat_bytes +- 8 KiB
-        return (8 * 4 * srng.integers((sat_bytes - (8 << 10)) // 4, (sat_bytes + (8 << 10)) // 4 + 1, k)).astype(np.uint64)
-    srv = mickey.Server(init, nslices=(nstates + 31) // 32, quantum_clocks=8192, budget_bytes=budget)
+    def sizes(k):  # bits: log-uniform 4 KiB .. max_bytes, whole 32-bit words
+        return (32 * np.floor(2.0 ** (lo + (hi - lo) * srng.random(k)) / 4)).astype(np.uint64)
+    nsl = (nstates + 31) // 32
+    srv = mickey.Server(init, nslices=nsl, quantum_clocks=8192, budget_bytes=budget)
+    srv.set_chunk(chunk)
     all_s = np.arange(nstates, dtype=np.uint32)
-    sid_of = np.zeros(1 << 25, dtype=np.uint32)  # request id -> state id
+    sid_of = np.zeros(1 << 23, dtype=np.uint32)  # request id -> state id
     ids0 = srv.submit_many(all_s, sizes(nstates))
     sid_of[ids0] = all_s
     t_start = time.monotonic_ns()
-    b0 = None
+    b0 = tb0 = st0 = None
+    nchunks = 0
     while True:
         srv.step()
-        ids = srv.poll()
+        ch = srv.poll_chunks(1 << 20)
+        if len(ch):
+            nchunks += len(ch)
+            srv.release_chunks(ch["handle"])  # the consumer has taken the chunk
+        ids = srv.poll(1 << 20)
         if len(ids):
-            srv.release_many(ids)
             again = sid_of[ids]
             new = srv.submit_many(again, sizes(len(again)))
             if new.max() >= len(sid_of):
                 sid_of = np.concatenate([sid_of, np.zeros_like(sid_of)])
             sid_of[new] = again
         el = (time.monotonic_ns() - t_start) * 1e-9
-        if b0 is None and el > 1.0:  # warm-up second
-            b0, tb0 = srv.stats()["bits_delivered"], time.monotonic_ns()
-        if b0 is not None and el > 1.0 + sat_seconds:
+        st = srv.stats()
+        if b0 is None and el > 2.0 and st["steps"] >= 40:  # warm-up
+            b0, tb0, st0, c0 = st["bits_delivered"], time.monotonic_ns(), st, nchunks
+        if b0 is not None and (time.monotonic_ns() - tb0) * 1e-9 > sat_seconds:
             break
-    srv.wait()
-    b1, tb1 = srv.stats()["bits_delivered"], time.monotonic_ns()
-    st = srv.stats()
+    b1, tb1, st1 = st["bits_delivered"], time.monotonic_ns(), st
     srv.close()
-    served = (b1 - b0) / ((tb1 - tb0) * 1e-9) / 1e9
-    # plain kernel on the same 10^6 instances, row-major, for the same per-instance length
+    win = (tb1 - tb0) * 1e-9
+    served = (b1 - b0) / win / 1e9
+    # plain kernel on the same 10^6 instances, row-major
+    pbits = 65536
     stream = torch.cuda.current_stream()
-    buf = torch.empty((nstates, sat_bits // 32), dtype=torch.int32, device="cuda")
-    init.generate(sat_bits, mickey.ROWMAJOR_U32, buf)
+    buf = torch.empty((nstates, pbits // 32), dtype=torch.int32, device="cuda")
+    init.generate(pbits, mickey.ROWMAJOR_U32, buf)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    init.generate(sat_bits, mickey.ROWMAJOR_U32, buf)
+    init.generate(pbits, mickey.ROWMAJOR_U32, buf)
     e1.record(stream)
     torch.cuda.synchronize()
-    plain = nstates * sat_bits / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    plain = nstates * pbits / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del buf
     init.close()
+
+    def d(k):
+        return (st1[k] - st0[k]) * 1e-9
     out["closed_loop"] = {
-        "workload": "every one of the 10^6 states keeps one request of %d+-8 KiB in flight (resubmitted on "
-                    "completion), %d slots, quantum 8192 clocks, measured over %.1f s after 1 s warm-up" % (
-                        sat_bytes >> 10, (nstates + 31) // 32, sat_seconds),
+        "workload": "every one of the 10^6 states keeps one request in flight (resubmitted on completion), size "
+                    "log-uniform 4 KiB..%d KiB, %d KiB chunks through the 64 GiB budget, %d slots x 32 lanes, "
+                    "quantum 8192 clocks; measured over %.1f s after a 2 s warm-up" % (
+                        max_bytes >> 10, chunk >> 10, nsl, win),
         "served_gbit_s": round(served, 3), "plain_same_instances_gbit_s": round(plain, 3),
-        "served_over_plain": round(served / plain, 4), "steps": st["steps"],
-        "host_s": {"blocked_on_gpu": round(st["host_wait_ns"] * 1e-9, 3),
-                   "retiring": round(st["host_retire_ns"] * 1e-9, 3),
-                   "admitting": round(st["host_admit_ns"] * 1e-9, 3),
-                   "client_and_other": round((tb1 - t_start) * 1e-9 - (st["host_wait_ns"] + st["host_retire_ns"]
-                                                                          + st["host_admit_ns"]) * 1e-9, 3)},
+        "served_over_plain": round(served / plain, 4),
+        "chunks_per_s": round((nchunks - c0) / win), "steps_in_window": st1["steps"] - st0["steps"],
+        "host_s_in_window": {"blocked_on_gpu": round(d("host_wait_ns"), 3), "retiring": round(d("host_retire_ns"), 3),
+                             "admitting": round(d("host_admit_ns"), 3),
+                             "client_and_other": round(win - d("host_wait_ns") - d("host_retire_ns")
+                                                       - d("host_admit_ns"), 3)},
     }
     print("# serve closed loop: %.1f Gbit/s served vs %.1f plain" % (served, plain), file=sys.stderr, flush=True)
     return out

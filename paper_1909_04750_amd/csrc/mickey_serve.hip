@@ -23,6 +23,7 @@
 // between chunks are admitted before new ones.  The client reads each finished chunk
 // and gives its space back, so the budget bounds the output in flight, not the size of
 // a request.
+#include "arena.h"
 #include "mickey_device.h"
 #include "mickey_host.h"
 
@@ -34,6 +35,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <queue>
 #include <unordered_map>
 #include <new>
 #include <vector>
@@ -163,6 +165,8 @@ struct Request {
     uint32_t lane = kNoRequest;
     uint32_t chunk_words = 0;  // 0: whole-request delivery
     size_t out_off = 0;        // word offset in the arena of the output (or current chunk)
+    size_t out_granted = 0;    // arena words held by it
+    uint64_t next_same = ~0ull;  // next request waiting on the same state
     uint64_t words_admitted = 0, words_done = 0;
     uint32_t cur_words = 0;    // words of the admission in flight
     bool refused = false;      // passed 2^40 bits
@@ -172,85 +176,9 @@ struct Request {
 
 // A delivered chunk's arena block, by handle.
 struct ChunkSlot {
-    size_t off = 0;
-    uint64_t words = 0;
+    size_t off = 0, granted = 0;  // arena block
+    uint64_t words = 0;           // keystream words in it
     bool live = false;
-};
-
-// Output-arena allocator, in 32-bit words: released blocks go to exact-size free lists
-// (O(1) reuse by requests of the same size); other sizes are carved first-fit from an
-// ordered map of coalesced free blocks, into which the size lists are flushed when the
-// map has no fitting block.
-struct Arena {
-    size_t capacity = 0;
-    size_t cached = 0;                                   // words held in the size lists
-    std::map<size_t, size_t> free_by_off;                // offset -> length, coalesced
-    std::unordered_map<size_t, std::vector<size_t>> by_size;  // length -> offsets
-    void reset(size_t words)
-    {
-        capacity = words;
-        cached = 0;
-        free_by_off.clear();
-        by_size.clear();
-        free_by_off[0] = words;
-    }
-    bool first_fit(size_t words, size_t *off)
-    {
-        for (auto it = free_by_off.begin(); it != free_by_off.end(); ++it) {
-            if (it->second >= words) {
-                *off = it->first;
-                const size_t rest = it->second - words, start = it->first + words;
-                free_by_off.erase(it);
-                if (rest) free_by_off[start] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void insert_coalesced(size_t off, size_t words)
-    {
-        auto it = free_by_off.emplace(off, words).first;
-        auto nx = std::next(it);
-        if (nx != free_by_off.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_by_off.erase(nx);
-        }
-        if (it != free_by_off.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_by_off.erase(it);
-            }
-        }
-    }
-    bool alloc(size_t words, size_t *off)
-    {
-        auto hit = by_size.find(words);
-        if (hit != by_size.end() && !hit->second.empty()) {
-            *off = hit->second.back();
-            hit->second.pop_back();
-            cached -= words;
-            return true;
-        }
-        if (first_fit(words, off)) return true;
-        if (!cached) return false;
-        for (auto &kv : by_size)
-            for (size_t o : kv.second) insert_coalesced(o, kv.first);
-        by_size.clear();
-        cached = 0;
-        return first_fit(words, off);
-    }
-    void release(size_t off, size_t words)
-    {
-        by_size[words].push_back(off);
-        cached += words;
-    }
-    size_t free_words() const
-    {
-        size_t f = cached;
-        for (auto &kv : free_by_off) f += kv.second;
-        return f;
-    }
 };
 
 uint64_t now_ns()
@@ -274,7 +202,7 @@ struct mickey_server {
     uint32_t *done_list = nullptr, *done_count = nullptr;
     Admit *dadm = nullptr;
     uint32_t *arena = nullptr;
-    Arena alloc;
+    serve_arena::Arena alloc;
     // host side
     Admit *hadm = nullptr;          // pinned
     // Two quanta can be in flight: quantum q uses completion buffer q & 1.
@@ -286,9 +214,14 @@ struct mickey_server {
     uint64_t next_q = 0, oldest_q = 0;  // quanta [oldest_q, next_q) are in flight
     uint32_t pending = 0;               // admissions decided, not yet enqueued
     std::vector<uint64_t> state_bits;
-    std::vector<uint8_t> state_busy;
+    // A state is owned by at most one request that is ready, running or between chunks;
+    // later requests on it wait in a chain (per-state FIFO through Request::next_same).
+    std::vector<uint8_t> state_owned;
+    std::vector<uint64_t> chain_head, chain_tail;
+    uint64_t chained = 0;
     std::vector<uint32_t> free_lanes;
-    std::deque<uint64_t> waiting;  // request ids in arrival order
+    // requests that own their state and wait for a lane and budget, oldest (lowest id) first
+    std::priority_queue<uint64_t, std::vector<uint64_t>, std::greater<uint64_t>> ready_q;
     std::vector<Request> reqs;     // by id
     std::vector<uint64_t> lane_req;
     std::vector<uint64_t> completed;  // not yet reported
@@ -325,6 +258,21 @@ __global__ void reset_count_kernel(uint32_t *c)
     if (threadIdx.x == 0) *c = 0u;
 }
 
+// The request owning state sid is done: the next request waiting on it (if any) becomes
+// ready, otherwise the state is free.
+void pass_state(mickey_server *s, uint32_t sid)
+{
+    const uint64_t nx = s->chain_head[sid];
+    if (nx == ~0ull) {
+        s->state_owned[sid] = 0;
+        return;
+    }
+    s->chain_head[sid] = s->reqs[nx].next_same;
+    if (s->chain_head[sid] == ~0ull) s->chain_tail[sid] = ~0ull;
+    s->chained--;
+    s->ready_q.push(nx);
+}
+
 // Wait for the oldest in-flight quantum and retire the requests it completed.
 int retire_oldest(mickey_server *s)
 {
@@ -359,7 +307,7 @@ int retire_oldest(mickey_server *s)
                 h = s->slots.size();
                 s->slots.emplace_back();
             }
-            s->slots[h] = ChunkSlot{r.out_off, r.cur_words, true};
+            s->slots[h] = ChunkSlot{r.out_off, r.out_granted, r.cur_words, true};
             s->ready.push_back(mickey_chunk{r.id, h, r.words_done - r.cur_words, r.cur_words, s->arena + r.out_off,
                                             last ? 1ull : 0ull});
         }
@@ -370,9 +318,9 @@ int retire_oldest(mickey_server *s)
         }
         r.done = true;
         r.done_ns = t1;
-        s->state_busy[r.sid] = 0;
         s->completed.push_back(r.id);
         s->finished++;
+        pass_state(s, r.sid);
     }
     s->ns_retire += now_ns() - t1;
     return MICKEY_OK;
@@ -384,12 +332,13 @@ bool admit_next(mickey_server *s, Request &r, uint64_t t_admit)
 {
     const uint64_t left = r.nbits / 32 - r.words_admitted;
     const uint32_t words = r.chunk_words ? (uint32_t)std::min<uint64_t>(left, r.chunk_words) : (uint32_t)left;
-    size_t off = 0;
-    if (s->free_lanes.empty() || !s->alloc.alloc(words, &off)) return false;
+    size_t off = 0, granted = 0;
+    if (s->free_lanes.empty() || !s->alloc.alloc(words, &off, &granted)) return false;
     const uint32_t lane = s->free_lanes.back();
     s->free_lanes.pop_back();
     r.lane = lane;
     r.out_off = off;
+    r.out_granted = granted;
     r.cur_words = words;
     r.words_admitted += words;
     if (!r.admit_ns) r.admit_ns = t_admit;
@@ -400,8 +349,9 @@ bool admit_next(mickey_server *s, Request &r, uint64_t t_admit)
 }
 
 // Decide admissions into s->hadm (enqueued by the next step): first the chunked requests
-// that are between two chunks (oldest first), then waiting requests in arrival order;
-// requests on busy states keep their place.
+// that are between two chunks (oldest first), then ready requests in arrival order, while
+// lanes and budget last.  Each request considered is admitted, refused (2^40 bits) or
+// left for later, so the cost is proportional to the admissions.
 void decide_admissions(mickey_server *s)
 {
     const uint64_t t_admit = now_ns();
@@ -413,28 +363,20 @@ void decide_admissions(mickey_server *s)
         }
         s->continuing.pop_front();
     }
-    std::deque<uint64_t> keep;
-    for (uint64_t id : s->waiting) {
-        Request &r = s->reqs[id];
-        if (full || s->state_busy[r.sid]) {
-            keep.push_back(id);
-            continue;
-        }
+    while (!full && !s->ready_q.empty()) {
+        Request &r = s->reqs[s->ready_q.top()];
         if (s->state_bits[r.sid] + r.nbits > MICKEY_MAX_BITS_PER_IV) {  // 2^40 per key/IV pair
+            s->ready_q.pop();
             r.done = true;
             r.refused = true;
             r.done_ns = t_admit;
             s->completed.push_back(r.id);
+            pass_state(s, r.sid);
             continue;
         }
-        if (!admit_next(s, r, t_admit)) {  // slots or budget full
-            full = true;
-            keep.push_back(id);
-            continue;
-        }
-        s->state_busy[r.sid] = 1;
+        if (!admit_next(s, r, t_admit)) break;  // slots or budget full
+        s->ready_q.pop();
     }
-    s->waiting.swap(keep);
     s->ns_admit += now_ns() - t_admit;
 }
 
@@ -508,7 +450,9 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
     }
     s->alloc.reset(budget_words);
     s->state_bits.assign(s->nstates, mickey_bits_generated(init));
-    s->state_busy.assign(s->nstates, 0);
+    s->state_owned.assign(s->nstates, 0);
+    s->chain_head.assign(s->nstates, ~0ull);
+    s->chain_tail.assign(s->nstates, ~0ull);
     s->free_lanes.resize(s->nlanes);
     for (size_t i = 0; i < s->nlanes; i++) s->free_lanes[i] = (uint32_t)(s->nlanes - 1 - i);
     s->lane_req.assign(s->nlanes, ~0ull);
@@ -533,7 +477,17 @@ int64_t mickey_server_submit(mickey_server *s, uint32_t state_id, uint64_t nbits
     r.chunk_words = s->chunk_words;
     r.arrival_ns = now_ns();
     s->reqs.push_back(r);
-    s->waiting.push_back(r.id);
+    if (!s->state_owned[state_id]) {
+        s->state_owned[state_id] = 1;
+        s->ready_q.push(r.id);
+    } else {  // behind the state's current request
+        if (s->chain_tail[state_id] == ~0ull)
+            s->chain_head[state_id] = r.id;
+        else
+            s->reqs[s->chain_tail[state_id]].next_same = r.id;
+        s->chain_tail[state_id] = r.id;
+        s->chained++;
+    }
     ok();
     return (int64_t)r.id;
 }
@@ -674,7 +628,7 @@ int mickey_server_release(mickey_server *s, uint64_t id)
     Request &r = s->reqs[id];
     if (!r.done || r.refused || r.released || r.chunk_words)
         return fail(MICKEY_EINVAL, "mickey_server_release: nothing to release");
-    s->alloc.release(r.out_off, r.nbits / 32);
+    s->alloc.release(r.out_off, r.out_granted);
     r.released = true;
     return ok();
 }
@@ -688,7 +642,7 @@ int mickey_server_stats(const mickey_server *s, uint64_t out[11])
 {
     if (!s || !out) return fail(MICKEY_EINVAL, "mickey_server_stats: bad argument");
     const size_t freew = s->alloc.free_words();
-    out[0] = s->waiting.size() + s->continuing.size();
+    out[0] = s->ready_q.size() + s->chained + s->continuing.size();
     out[1] = s->nlanes - s->free_lanes.size();
     out[2] = s->admitted;
     out[3] = s->finished;
@@ -756,7 +710,7 @@ int mickey_server_release_chunks(mickey_server *s, const uint64_t *handles, size
                              (unsigned long long)h);
             continue;
         }
-        s->alloc.release(s->slots[h].off, s->slots[h].words);
+        s->alloc.release(s->slots[h].off, s->slots[h].granted);
         s->slots[h].live = false;
         s->free_slots.push_back(h);
     }
