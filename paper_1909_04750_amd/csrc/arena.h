@@ -11,10 +11,10 @@ namespace serve_arena {
 // Output-arena allocator, in 32-bit words.  A request is rounded up to a size class with
 // three significant bits (exact up to 8 words, then steps of 1/8 of a power of two, so at
 // most 12.5% of a block is unused); each class keeps a stack of free blocks, and new blocks
-// are cut from the top of the arena.  When neither serves, a free block of a larger class
-// is split (its remainder joins a first-fit list of spare blocks), and as a last resort
-// every free block is merged with its neighbours into that list (and the top lowered)
-// before the allocation is retried.  Alloc
+// are cut from the top of the arena.  When neither serves, a first-fit list of spare
+// blocks is tried, then every free block is merged with its neighbours into that list
+// (and the top lowered when the highest free block reaches it) and the allocation is
+// retried; a block of a larger class is split only after that.  Alloc
 // and release are O(1) in the steady state.
 struct Arena {
     size_t capacity = 0, top = 0;
@@ -75,42 +75,40 @@ struct Arena {
                 spare[o] = w;
         }
     }
-    // On success *granted is the block size to pass back to release().
+    // On success *granted is the block size to pass back to release().  Order: a block of
+    // the exact class, the top, a spare block (first fit, low offsets first); failing
+    // those, merge all free space and try again; splitting a larger class's block comes
+    // last, because merging keeps the free space in fewer, larger pieces.
     bool alloc(size_t words, size_t *off, size_t *granted)
     {
         const int c = cls(words);
         const size_t need = class_words(c);
+        *granted = need;
         for (int pass = 0; pass < 2; pass++) {
             if (!lists[c].empty()) {
                 *off = lists[c].back();
                 lists[c].pop_back();
                 listed -= need;
-                *granted = need;
                 return true;
             }
             if (top + need <= capacity) {
                 *off = top;
                 top += need;
-                *granted = need;
                 return true;
             }
-            if (!spare.empty() && from_spare(need, off)) {
-                *granted = need;
-                return true;
-            }
-            for (size_t b = c + 1; b < lists.size(); b++) {
-                if (!lists[b].empty()) {  // split a block of a larger class
-                    *off = lists[b].back();
-                    lists[b].pop_back();
-                    const size_t bw = class_words((int)b);
-                    listed -= bw;
-                    spare[*off + need] = bw - need;
-                    *granted = need;
-                    return true;
-                }
-            }
+            if (!spare.empty() && from_spare(need, off)) return true;
             if (pass == 0 && listed) merge_all();
             else break;
+        }
+        for (size_t b = c + 1; b < lists.size(); b++) {
+            if (!lists[b].empty()) {  // split a block of a larger class
+                *off = lists[b].back();
+                lists[b].pop_back();
+                const size_t bw = class_words((int)b);
+                listed -= bw;
+                spare[*off + need] = bw - need;
+                return true;
+            }
         }
         return false;
     }

@@ -48,6 +48,17 @@ int main()
     for (auto &kv : live) a.release(kv.first, kv.second);
     size_t off, g;
     if (!a.alloc(cap, &off, &g) || off != 0) { printf("BAD final\n"); return 1; }
+    // small budget: four 128-word blocks come and go, then a 2-word block stays while a
+    // 208-word class must still fit beside it
+    serve_arena::Arena b;
+    b.reset(256);
+    size_t o[4], gg;
+    for (int r = 0; r < 2; r++) {
+        for (int i = 0; i < 2; i++) if (!b.alloc(128, &o[i], &gg)) { printf("BAD small 1\n"); return 1; }
+        for (int i = 0; i < 2; i++) b.release(o[i], 128);
+    }
+    size_t a1, a2;
+    if (!b.alloc(2, &a1, &gg) || !b.alloc(200, &a2, &gg) || gg != 208) { printf("BAD small 2\n"); return 1; }
     printf("ok fails=%ld\n", fails);
     return 0;
 }
