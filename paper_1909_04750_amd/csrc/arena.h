@@ -21,6 +21,8 @@ struct Arena {
     size_t listed = 0;                            // words in the class stacks
     std::vector<std::vector<size_t>> lists;       // per class: block offsets
     std::map<size_t, size_t> spare;               // merged free blocks: offset -> words
+    size_t spare_words = 0;
+    bool released_since_merge = false;            // a merge can only help after a release
 
     static int cls(size_t w)
     {
@@ -42,6 +44,8 @@ struct Arena {
         listed = 0;
         lists.assign(cls(words) + 2, {});
         spare.clear();
+        spare_words = 0;
+        released_since_merge = false;
     }
     bool from_spare(size_t need, size_t *off)
     {
@@ -51,6 +55,7 @@ struct Arena {
                 const size_t rest = it->second - need, start = it->first + need;
                 spare.erase(it);
                 if (rest) spare[start] = rest;
+                spare_words -= need;
                 return true;
             }
         }
@@ -65,14 +70,18 @@ struct Arena {
         for (auto &l : lists) l.clear();
         listed = 0;
         spare.clear();
+        spare_words = 0;
+        released_since_merge = false;
         std::sort(blocks.begin(), blocks.end());
         for (size_t i = 0; i < blocks.size();) {
             size_t o = blocks[i].first, w = blocks[i].second;
             for (i++; i < blocks.size() && blocks[i].first == o + w; i++) w += blocks[i].second;
-            if (o + w == top)
+            if (o + w == top) {
                 top = o;
-            else
+            } else {
                 spare[o] = w;
+                spare_words += w;
+            }
         }
     }
     // On success *granted is the block size to pass back to release().  Order: a block of
@@ -96,8 +105,8 @@ struct Arena {
                 top += need;
                 return true;
             }
-            if (!spare.empty() && from_spare(need, off)) return true;
-            if (pass == 0 && listed) merge_all();
+            if (spare_words >= need && from_spare(need, off)) return true;
+            if (pass == 0 && released_since_merge && listed + spare_words >= need) merge_all();
             else break;
         }
         for (size_t b = c + 1; b < lists.size(); b++) {
@@ -107,6 +116,7 @@ struct Arena {
                 const size_t bw = class_words((int)b);
                 listed -= bw;
                 spare[*off + need] = bw - need;
+                spare_words += bw - need;
                 return true;
             }
         }
@@ -116,12 +126,11 @@ struct Arena {
     {
         lists[cls(granted)].push_back(off);
         listed += granted;
+        released_since_merge = true;
     }
     size_t free_words() const
     {
-        size_t f = capacity - top + listed;
-        for (auto &kv : spare) f += kv.second;
-        return f;
+        return capacity - top + listed + spare_words;
     }
 };
 

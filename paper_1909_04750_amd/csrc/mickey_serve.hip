@@ -332,8 +332,10 @@ bool admit_next(mickey_server *s, Request &r, uint64_t t_admit)
 {
     const uint64_t left = r.nbits / 32 - r.words_admitted;
     const uint32_t words = r.chunk_words ? (uint32_t)std::min<uint64_t>(left, r.chunk_words) : (uint32_t)left;
+    // a chunk always reserves a whole chunk, so that chunk blocks share one size class
+    const size_t reserve = r.chunk_words ? r.chunk_words : words;
     size_t off = 0, granted = 0;
-    if (s->free_lanes.empty() || !s->alloc.alloc(words, &off, &granted)) return false;
+    if (s->free_lanes.empty() || !s->alloc.alloc(reserve, &off, &granted)) return false;
     const uint32_t lane = s->free_lanes.back();
     s->free_lanes.pop_back();
     r.lane = lane;
