@@ -10,7 +10,8 @@
 //      budget allows (a request reserves its whole output, or in chunked delivery one
 //      chunk at a time; a state runs at most one request at a time, so requests on one
 //      state run in arrival order),
-//   3. gathers the admitted states into their lane bits, and
+//   3. flags the admitted lanes (the next quantum gathers their states into its
+//      registers), and
 //   4. runs one quantum of Q clocks on every occupied slice, writing each request's
 //      keystream as row-major words (MICKEY_ROWMAJOR_U32 layout) into its output.
 // Requests that arrive while others run join at the next quantum, next to them.
@@ -56,29 +57,42 @@ struct Admit {
     uint32_t *out;
 };
 
-// Gather: write the packed state `sid` into bit lane%32 of word lane/32 of every plane,
-// and set the lane's output metadata.  Lanes of one slice may be admitted in the same
-// launch, so the plane words are updated with atomics.
+// Admission metadata: lane `lane` takes resident state `sid` with an output of `words`
+// words at `out`, and is flagged fresh in its slice's mask (one atomic per admission); the
+// next quantum gathers the fresh lanes' states into its registers.
 __global__ __launch_bounds__(256) void admit_kernel(const Admit *__restrict__ adm, uint32_t nadm,
-                                                    const uint8_t *__restrict__ pool, uint32_t *__restrict__ planes,
-                                                    uint32_t nslices, uint32_t **lane_out, uint32_t *lane_left,
-                                                    uint32_t *lane_sid)
+                                                    uint32_t **lane_out, uint32_t *lane_left, uint32_t *lane_sid,
+                                                    uint32_t *fresh)
 {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nadm) return;
     const Admit a = adm[k];
-    const uint32_t g = a.lane >> 5, bit = 1u << (a.lane & 31u);
-    const uint8_t *p = pool + 25ull * a.sid;
-    for (int j = 0; j < 200; j++) {
-        uint32_t *w = planes + (size_t)j * nslices + g;
-        if ((p[j >> 3] >> (7 - (j & 7))) & 1u)
-            atomicOr(w, bit);
-        else
-            atomicAnd(w, ~bit);
-    }
     lane_out[a.lane] = a.out;
     lane_left[a.lane] = a.words;
     lane_sid[a.lane] = a.sid;
+    atomicOr(fresh + (a.lane >> 5), 1u << (a.lane & 31u));
+}
+
+// Replace bit l of the 200 state words with the packed state at src (25 bytes, r_0..r_99
+// then s_0..s_99, most significant bit first).
+__device__ __forceinline__ void gather_lane(Regs<1> &x, uint32_t l, const uint8_t *src)
+{
+    uint32_t w[7];
+#pragma unroll
+    for (int k = 0; k < 7; k++) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++) v = (v << 8) | (4 * k + b < 25 ? (uint32_t)src[4 * k + b] : 0u);
+        w[k] = v;
+    }
+    const uint32_t m = 1u << l;
+    constexpr int kSel = (TA & ~TB & 0xFF) | (TC & TB);  // b ? c : a
+#pragma unroll
+    for (int j = 0; j < 200; j++) {
+        const uint32_t bit = 0u - ((w[j >> 5] >> (31 - (j & 31))) & 1u);
+        Word<1> &dst = j < 100 ? x.r[j] : x.s[j - 100];
+        dst.w[0] = __builtin_amdgcn_bitop3_b32(dst.w[0], m, bit, kSel);
+    }
 }
 
 // Pack bit l of the 200 state words into 25 bytes at dst (MSB first).
@@ -105,7 +119,7 @@ __device__ __forceinline__ void write_back_lane(const Regs<1> &x, uint32_t l, ui
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void quantum_kernel(
     uint32_t *__restrict__ planes, uint32_t nslices, uint32_t nblocks, uint32_t **lane_out,
     uint32_t *__restrict__ lane_left, const uint32_t *__restrict__ lane_sid, uint8_t *__restrict__ pool,
-    uint32_t *__restrict__ done_list, uint32_t *__restrict__ done_count)
+    uint32_t *__restrict__ fresh, uint32_t *__restrict__ done_list, uint32_t *__restrict__ done_count)
 {
     __shared__ uint32_t zbuf[32][64];
     __shared__ uint32_t *s_out[32][64];
@@ -126,6 +140,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     const uint32_t voff = g * 4u;
     Regs<1> x;
     load_state<1>(x, planes, pitch, voff);
+    uint32_t fr = fresh[g];  // lanes admitted since the last quantum: gather their states
+    if (fr) {
+        fresh[g] = 0u;
+        while (fr) {
+            const uint32_t l = (uint32_t)__builtin_ctz(fr);
+            fr &= fr - 1u;
+            gather_lane(x, l, pool + 25ull * lane_sid[g * 32u + l]);
+        }
+    }
     uint32_t blk = 0;
     for (; blk < nblocks && active; blk++) {
         rowmajor_block<kServeUnroll>(x, zbuf, tid, [&](int l, uint32_t w) {
@@ -199,6 +222,7 @@ struct mickey_server {
     uint32_t *planes = nullptr;
     uint32_t **lane_out = nullptr;
     uint32_t *lane_left = nullptr, *lane_sid = nullptr;
+    uint32_t *fresh = nullptr;  // per slice: lanes admitted since the last quantum
     uint32_t *done_list = nullptr, *done_count = nullptr;
     Admit *dadm = nullptr;
     uint32_t *arena = nullptr;
@@ -241,7 +265,8 @@ void destroy(mickey_server *s)
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (void *p : {(void *)s->pool, (void *)s->planes, (void *)s->lane_out, (void *)s->lane_left,
-                    (void *)s->lane_sid, (void *)s->done_list, (void *)s->dadm, (void *)s->arena})
+                    (void *)s->lane_sid, (void *)s->fresh, (void *)s->done_list, (void *)s->dadm,
+                    (void *)s->arena})
         if (p) (void)hipFree(p);
     if (s->hadm) (void)hipHostFree(s->hadm);
     if (s->hcount) (void)hipHostFree(s->hcount);
@@ -422,6 +447,7 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
                hipMalloc(&s->lane_out, s->nlanes * sizeof(uint32_t *)) == hipSuccess &&
                hipMalloc(&s->lane_left, s->nlanes * 4) == hipSuccess &&
                hipMalloc(&s->lane_sid, s->nlanes * 4) == hipSuccess &&
+               hipMalloc(&s->fresh, s->nslices * 4) == hipSuccess &&
                hipMalloc(&s->done_list, 256) == hipSuccess &&
                hipMalloc(&s->dadm, s->nlanes * sizeof(Admit)) == hipSuccess &&
                hipMalloc(&s->arena, budget_words * 4) == hipSuccess &&
@@ -442,6 +468,7 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
     // the initial states: the registers of the given initialised instances
     int rc = mickey_state_export(init, s->pool, nullptr);
     if (rc == MICKEY_OK && (hipMemsetAsync(s->lane_left, 0, s->nlanes * 4) != hipSuccess ||
+                            hipMemsetAsync(s->fresh, 0, s->nslices * 4) != hipSuccess ||
                             hipMemsetAsync(s->planes, 0, 200 * s->nslices * 4) != hipSuccess ||
                             hipDeviceSynchronize() != hipSuccess))
         rc = check_launch("mickey_server_create");
@@ -505,8 +532,7 @@ int mickey_server_step(mickey_server *s)
             hipSuccess)
             return check_launch("admission upload");
         hipLaunchKernelGGL(admit_kernel, dim3((s->pending + 255) / 256), dim3(256), 0, s->stream, s->dadm,
-                           s->pending, s->pool, s->planes, (uint32_t)s->nslices, s->lane_out, s->lane_left,
-                           s->lane_sid);
+                           s->pending, s->lane_out, s->lane_left, s->lane_sid, s->fresh);
         rc = check_launch("admit_kernel");
         if (rc != MICKEY_OK) return rc;
         s->pending = 0;
@@ -518,7 +544,7 @@ int mickey_server_step(mickey_server *s)
         s->launch_ns[b] = now_ns();
         hipLaunchKernelGGL(quantum_kernel, dim3((unsigned)(s->nslices / 64)), dim3(64), 0, s->stream, s->planes,
                            (uint32_t)s->nslices, s->qblocks, s->lane_out, s->lane_left, s->lane_sid, s->pool,
-                           s->hlist_dev + (size_t)b * s->nlanes, s->done_count + b);
+                           s->fresh, s->hlist_dev + (size_t)b * s->nlanes, s->done_count + b);
         rc = check_launch("quantum_kernel");
         if (rc != MICKEY_OK) return rc;
         if (hipMemcpyAsync(s->hcount + b, s->done_count + b, 4, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
