@@ -201,8 +201,15 @@ struct Request {
 struct ChunkSlot {
     size_t off = 0, granted = 0;  // arena block
     uint64_t words = 0;           // keystream words in it
+    uint32_t slice = 0;           // slice of the lane that wrote it
     bool live = false;
 };
+
+// Released chunk blocks are kept per slice (up to this many) and handed to the next chunk
+// admitted into the same slice, so the 32 lanes of a slice keep writing into a few nearby
+// blocks (the blocks first handed out to a slice are adjacent) instead of blocks spread
+// over the whole arena: fewer pages touched per store instruction.
+constexpr size_t kSliceCache = 48;
 
 uint64_t now_ns()
 {
@@ -253,6 +260,8 @@ struct mickey_server {
     std::deque<uint64_t> continuing;  // chunked requests between two chunks, oldest first
     std::vector<mickey_chunk> ready;  // delivered chunks not yet polled
     std::vector<ChunkSlot> slots;     // chunk handles
+    std::vector<std::vector<std::pair<size_t, size_t>>> slice_blocks;  // per slice: (offset, granted)
+    size_t slice_cached = 0;          // words held there
     std::vector<uint64_t> free_slots;
     uint64_t steps = 0, quanta_ns = 0, admitted = 0, finished = 0, bits_done = 0;
     uint64_t ns_wait = 0, ns_retire = 0, ns_admit = 0;  // host time spent in each part
@@ -332,7 +341,7 @@ int retire_oldest(mickey_server *s)
                 h = s->slots.size();
                 s->slots.emplace_back();
             }
-            s->slots[h] = ChunkSlot{r.out_off, r.out_granted, r.cur_words, true};
+            s->slots[h] = ChunkSlot{r.out_off, r.out_granted, r.cur_words, lane / 32u, true};
             s->ready.push_back(mickey_chunk{r.id, h, r.words_done - r.cur_words, r.cur_words, s->arena + r.out_off,
                                             last ? 1ull : 0ull});
         }
@@ -359,9 +368,25 @@ bool admit_next(mickey_server *s, Request &r, uint64_t t_admit)
     const uint32_t words = r.chunk_words ? (uint32_t)std::min<uint64_t>(left, r.chunk_words) : (uint32_t)left;
     // a chunk always reserves a whole chunk, so that chunk blocks share one size class
     const size_t reserve = r.chunk_words ? r.chunk_words : words;
-    size_t off = 0, granted = 0;
-    if (s->free_lanes.empty() || !s->alloc.alloc(reserve, &off, &granted)) return false;
+    if (s->free_lanes.empty()) return false;
     const uint32_t lane = s->free_lanes.back();
+    size_t off = 0, granted = 0;
+    auto &cache = s->slice_blocks[lane / 32u];
+    const size_t cls_words = serve_arena::Arena::class_words(serve_arena::Arena::cls(reserve));
+    if (r.chunk_words && !cache.empty() && cache.back().second == cls_words) {
+        off = cache.back().first;
+        granted = cache.back().second;
+        cache.pop_back();
+        s->slice_cached -= granted;
+    } else if (!s->alloc.alloc(reserve, &off, &granted)) {
+        if (!s->slice_cached) return false;
+        for (auto &c : s->slice_blocks) {  // give every cached block back and retry once
+            for (auto &b : c) s->alloc.release(b.first, b.second);
+            c.clear();
+        }
+        s->slice_cached = 0;
+        if (!s->alloc.alloc(reserve, &off, &granted)) return false;
+    }
     s->free_lanes.pop_back();
     r.lane = lane;
     r.out_off = off;
@@ -478,6 +503,7 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
         return nullptr;
     }
     s->alloc.reset(budget_words);
+    s->slice_blocks.assign(s->nslices, {});
     s->state_bits.assign(s->nstates, mickey_bits_generated(init));
     s->state_owned.assign(s->nstates, 0);
     s->chain_head.assign(s->nstates, ~0ull);
@@ -669,7 +695,7 @@ int mickey_server_release(mickey_server *s, uint64_t id)
 int mickey_server_stats(const mickey_server *s, uint64_t out[11])
 {
     if (!s || !out) return fail(MICKEY_EINVAL, "mickey_server_stats: bad argument");
-    const size_t freew = s->alloc.free_words();
+    const size_t freew = s->alloc.free_words() + s->slice_cached;
     out[0] = s->ready_q.size() + s->chained + s->continuing.size();
     out[1] = s->nlanes - s->free_lanes.size();
     out[2] = s->admitted;
@@ -738,7 +764,13 @@ int mickey_server_release_chunks(mickey_server *s, const uint64_t *handles, size
                              (unsigned long long)h);
             continue;
         }
-        s->alloc.release(s->slots[h].off, s->slots[h].granted);
+        auto &cache = s->slice_blocks[s->slots[h].slice];
+        if (cache.size() < kSliceCache) {
+            cache.emplace_back(s->slots[h].off, s->slots[h].granted);
+            s->slice_cached += s->slots[h].granted;
+        } else {
+            s->alloc.release(s->slots[h].off, s->slots[h].granted);
+        }
         s->slots[h].live = false;
         s->free_slots.push_back(h);
     }
