@@ -68,7 +68,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
         for (uint32_t j = 0; j < nwords; j++) {
             rowmajor_block<U>(x, zbuf, tid, [&](int l, uint32_t w) {
                 const uint32_t slot = g * 32u + (uint32_t)l;
-                if (j < lane_words[slot]) lane_out[slot][j] = w;
+                if (j < lane_words[slot]) store_global(lane_out[slot] + j, w);
             });
         }
     }
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(64) void latency_kernel(const uint8_t *__restrict__
             acc = __builtin_amdgcn_alignbit(x.r[0] ^ x.s[0], acc, 1);  // z enters at bit 31
             wclock<false>(x, 0u);
         }
-        out[j] = __builtin_bitreverse32(acc);  // first bit of the word in the MSB
+        store_global(out + j, __builtin_bitreverse32(acc));  // first bit of the word in the MSB
     }
 }
 

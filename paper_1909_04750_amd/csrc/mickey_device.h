@@ -169,6 +169,17 @@ __device__ __forceinline__ void st_word(char *p, const Word<K> &v)
     }
 }
 
+// Output words always go to device memory.  Stores through pointers that were loaded
+// from memory would be flat stores, which also count against the LDS wait counter, so
+// every later LDS wait (the transposes) would wait for them; a global-address-space
+// pointer gives global stores.
+typedef __attribute__((address_space(1))) uint32_t global_u32;
+__device__ __forceinline__ void store_global(uint32_t *p, uint32_t v) { *(global_u32 *)p = v; }
+__device__ __forceinline__ void store_global_f32(float *p, float v)
+{
+    *(__attribute__((address_space(1))) float *)p = v;
+}
+
 // One keystream word (K 32-bit words) at the lane's offset in a wave-uniform plane: a
 // vector buffer store whose resource is built from the scalar plane address, so that the
 // per-clock address arithmetic stays on the scalar unit.

@@ -152,7 +152,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     uint32_t blk = 0;
     for (; blk < nblocks && active; blk++) {
         rowmajor_block<kServeUnroll>(x, zbuf, tid, [&](int l, uint32_t w) {
-            if ((active >> l) & 1u) s_out[l][tid][blk] = w;
+            if ((active >> l) & 1u) store_global(s_out[l][tid] + blk, w);
         });
         uint32_t finished = 0;
         if (ends) {
