@@ -110,30 +110,35 @@ __device__ __forceinline__ void write_back_lane(const Regs<1> &x, uint32_t l, ui
     for (int b = 0; b < 25; b++) dst[b] = (uint8_t)(w[b >> 2] >> (24 - 8 * (b & 3)));
 }
 
-// One quantum of nblocks*32 clocks on every slice with an occupied lane bit.  Each
-// lane's output pointer and remaining words are read once into LDS; during the quantum
-// lane l stores block blk's word at out[l] + blk while blk < left[l], so the per-block
-// bookkeeping is read-only.  When a lane's request ends at the end of a block, its state
-// is packed back into the pool right there and the lane is appended to the completion
-// list; at the end of the quantum the pointers and counts move on by the blocks done.
+// One quantum of nblocks*32 clocks on every slice with an occupied lane bit.  Each lane's
+// output pointer and remaining words are read once into LDS and are read-only during the
+// quantum.  A block's 32 keystream words per lane are transposed in LDS (lane l's word in
+// row 31 - l), and during clock c of the next block the word of lane 31 - c is stored: its
+// pointer and word are read from LDS at the start of that clock and stored at its end, so
+// the LDS latency hides behind the clock's arithmetic (the last block is drained after the
+// loop).  One 32-row buffer holds both: at clock c, row c gives up its word and takes the
+// keystream plane of clock c.  A lane whose request
+// ends at the end of block b has its state packed back into the pool right there and is
+// appended to the completion list; the lanes' end blocks are only scanned when the next
+// one is reached.  At the end the pointers and counts move on by the blocks done.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void quantum_kernel(
     uint32_t *__restrict__ planes, uint32_t nslices, uint32_t nblocks, uint32_t **lane_out,
     uint32_t *__restrict__ lane_left, const uint32_t *__restrict__ lane_sid, uint8_t *__restrict__ pool,
-    uint32_t *__restrict__ fresh, uint32_t *__restrict__ done_list, uint32_t *__restrict__ done_count)
+    uint32_t *__restrict__ fresh, uint32_t *__restrict__ sink, uint32_t *__restrict__ done_list,
+    uint32_t *__restrict__ done_count)
 {
     __shared__ uint32_t zbuf[32][64];
     __shared__ uint32_t *s_out[32][64];
-    __shared__ uint32_t s_left[32][64];
     const uint32_t tid = threadIdx.x;
     const uint32_t g = blockIdx.x * 64u + tid;
     if (g >= nslices) return;  // no barriers: each lane touches only its own LDS columns
-    uint32_t active = 0, ends = 0;  // lanes with words left; lanes that end in this quantum
+    uint32_t active = 0;             // lanes with words left
+    uint32_t next_end = 0xFFFFFFFFu;  // the earliest block count at which a lane's request ends
     for (int l = 0; l < 32; l++) {
         const uint32_t left = lane_left[g * 32u + l];
-        s_left[l][tid] = left;
         s_out[l][tid] = lane_out[g * 32u + l];
         active |= (left ? 1u : 0u) << l;
-        ends |= (left && left <= nblocks ? 1u : 0u) << l;
+        if (left && left < next_end) next_end = left;
     }
     if (!active) return;
     const size_t pitch = (size_t)nslices * 4u;
@@ -149,17 +154,53 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
             gather_lane(x, l, pool + 25ull * lane_sid[g * 32u + l]);
         }
     }
+    uint32_t pend = 0;  // lanes with a word of block blk - 1 waiting in zprev
     uint32_t blk = 0;
     for (; blk < nblocks && active; blk++) {
-        rowmajor_block<kServeUnroll>(x, zbuf, tid, [&](int l, uint32_t w) {
-            if ((active >> l) & 1u) store_global(s_out[l][tid] + blk, w);
-        });
-        uint32_t finished = 0;
-        if (ends) {
-            for (uint32_t l = 0; l < 32; l++)
-                if (((ends >> l) & 1u) && s_left[l][tid] == blk + 1u) finished |= 1u << l;
+        for (int b0 = 0; b0 < 32; b0 += kServeUnroll) {
+#pragma unroll
+            for (int u = 0; u < kServeUnroll; u++) {
+                const int c = b0 + u, l = 31 - c;
+                const uint32_t w = zbuf[c][tid];  // word of lane l from the previous block
+                uint32_t *const p = s_out[l][tid];
+                zbuf[c][tid] = (x.r[0] ^ x.s[0]).w[0];  // row c now holds clock c
+                clock_gen<1>(x);
+                // The store goes after the clock's arithmetic (the scheduler may not move
+                // anything across the barrier), so the LDS loads above have the whole clock
+                // to complete; a lane without a word writes to the slice's sink word.
+                uint32_t *const dst = ((pend >> l) & 1u) ? p + (blk - 1u) : sink + g;
+                __builtin_amdgcn_sched_barrier(0);
+                store_global(dst, w);
+            }
         }
-        if (finished) {
+#pragma unroll
+        for (int h = 0; h < 32; h += 16) {
+            uint32_t a[16];
+#pragma unroll
+            for (int i = 0; i < 16; i++) a[i] = zbuf[31 - (h + i)][tid];  // row 31-r: clock r
+            transpose_half(a);
+#pragma unroll
+            for (int i = 0; i < 16; i++) zbuf[31 - (h + i)][tid] = a[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            uint32_t lo = zbuf[31 - i][tid], hi = zbuf[15 - i][tid];
+            swap_stage<16>(lo, hi);
+            zbuf[31 - i][tid] = lo;  // word of lane i (bit 31 - b = clock b of the block)
+            zbuf[15 - i][tid] = hi;  // word of lane i + 16
+        }
+        pend = active;
+        if (blk + 1u == next_end) {  // some lanes end with this block
+            uint32_t finished = 0;
+            next_end = 0xFFFFFFFFu;
+            for (uint32_t l = 0; l < 32; l++) {
+                if (!((active >> l) & 1u)) continue;
+                const uint32_t left = lane_left[g * 32u + l];
+                if (left == blk + 1u)
+                    finished |= 1u << l;
+                else if (left < next_end)
+                    next_end = left;
+            }
             for (uint32_t l = 0; l < 32; l++) {
                 if ((finished >> l) & 1u) {
                     write_back_lane(x, l, pool + 25ull * lane_sid[g * 32u + l]);
@@ -169,9 +210,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
             active &= ~finished;
         }
     }
+    for (int l = 0; l < 32; l++)  // drain the last block's words
+        if ((pend >> l) & 1u) store_global(s_out[l][tid] + (blk - 1u), zbuf[31 - l][tid]);
     store_state<1>(x, planes, pitch, voff);
     for (int l = 0; l < 32; l++) {
-        const uint32_t left = s_left[l][tid];
+        const uint32_t left = lane_left[g * 32u + l];
         if (!left) continue;
         const uint32_t done = left < blk ? left : blk;
         lane_left[g * 32u + l] = left - done;
@@ -230,6 +273,7 @@ struct mickey_server {
     uint32_t **lane_out = nullptr;
     uint32_t *lane_left = nullptr, *lane_sid = nullptr;
     uint32_t *fresh = nullptr;  // per slice: lanes admitted since the last quantum
+    uint32_t *sink = nullptr;   // per slice: target of stores by lanes without output
     uint32_t *done_list = nullptr, *done_count = nullptr;
     Admit *dadm = nullptr;
     uint32_t *arena = nullptr;
@@ -274,7 +318,7 @@ void destroy(mickey_server *s)
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (void *p : {(void *)s->pool, (void *)s->planes, (void *)s->lane_out, (void *)s->lane_left,
-                    (void *)s->lane_sid, (void *)s->fresh, (void *)s->done_list, (void *)s->dadm,
+                    (void *)s->lane_sid, (void *)s->fresh, (void *)s->sink, (void *)s->done_list, (void *)s->dadm,
                     (void *)s->arena})
         if (p) (void)hipFree(p);
     if (s->hadm) (void)hipHostFree(s->hadm);
@@ -473,6 +517,7 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
                hipMalloc(&s->lane_left, s->nlanes * 4) == hipSuccess &&
                hipMalloc(&s->lane_sid, s->nlanes * 4) == hipSuccess &&
                hipMalloc(&s->fresh, s->nslices * 4) == hipSuccess &&
+               hipMalloc(&s->sink, s->nslices * 4) == hipSuccess &&
                hipMalloc(&s->done_list, 256) == hipSuccess &&
                hipMalloc(&s->dadm, s->nlanes * sizeof(Admit)) == hipSuccess &&
                hipMalloc(&s->arena, budget_words * 4) == hipSuccess &&
@@ -570,7 +615,7 @@ int mickey_server_step(mickey_server *s)
         s->launch_ns[b] = now_ns();
         hipLaunchKernelGGL(quantum_kernel, dim3((unsigned)(s->nslices / 64)), dim3(64), 0, s->stream, s->planes,
                            (uint32_t)s->nslices, s->qblocks, s->lane_out, s->lane_left, s->lane_sid, s->pool,
-                           s->fresh, s->hlist_dev + (size_t)b * s->nlanes, s->done_count + b);
+                           s->fresh, s->sink, s->hlist_dev + (size_t)b * s->nlanes, s->done_count + b);
         rc = check_launch("quantum_kernel");
         if (rc != MICKEY_OK) return rc;
         if (hipMemcpyAsync(s->hcount + b, s->done_count + b, 4, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
