@@ -71,36 +71,52 @@ def cpu_baseline(keys, ivs, nbits, gpu_sample_bits, sample_idx, threads):
 
 def bench_rowmajor(torch, mickey, synth, reps: int = 3):
     """2^20 instances, IV lengths in {0,32,64,80}, 65536 bits each, in-kernel transpose to
-    row-major u32 plus exact f32 (16 GiB of output)."""
+    row-major u32 plus exact f32 (16 GiB of output).  2^20 instances are 512 waves at 32
+    instances per lane, a quarter of the device's two-per-SIMD wave slots: the default
+    (automatic) schedule splits each slice over two waves (R and S registers), and the
+    row-major words come from bit-plane chunks through a tiled transpose.  The fused
+    in-kernel transpose is timed beside it with both schedules."""
     seed, n, nbits, _ = synth.workload("rowmajor-1m")
     keys, ivs, ivb = synth.workload_inputs("rowmajor-1m")
     dk, dv, db = (torch.from_numpy(a).cuda() for a in (keys, ivs, ivb))
     stream = torch.cuda.current_stream()
-    m = mickey.Mickey(dk, dv, db, stream=stream)
     u = torch.empty((n, nbits // 32), dtype=torch.int32, device="cuda")
     f = torch.empty((n, nbits // 32), dtype=torch.float32, device="cuda")
-    m.generate_rowmajor(nbits, u, f)  # warm-up
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    t_init, t_gen = [], []
-    for _ in range(reps):
-        ev[0].record(stream)
-        m.rekey(dk, dv, db)
-        ev[1].record(stream)
-        m.generate_rowmajor(nbits, u, f)
-        ev[2].record(stream)
-        torch.cuda.synchronize()
-        t_init.append(ev[0].elapsed_time(ev[1]))
-        t_gen.append(ev[1].elapsed_time(ev[2]))
-    m.close()
-    step = float(np.mean(t_init) + np.mean(t_gen))
     bits = n * nbits
-    print("# rowmajor-1m: init %.3f ms, generate %.3f ms" % (np.mean(t_init), np.mean(t_gen)), file=sys.stderr,
-          flush=True)
-    return {"workload": "2^20 instances, IV lengths {0,32,64,80}, 65536 bits each, row-major u32 + f32",
-            "gbit_s": round(bits / (step * 1e-3) / 1e9, 3), "init_ms": round(float(np.mean(t_init)), 4),
-            "generate_ms": round(float(np.mean(t_gen)), 4),
-            "generate_gbit_s": round(bits / (np.mean(t_gen) * 1e-3) / 1e9, 3),
-            "waves": n // 32 // 64, "note": "2^20 instances fill 512 of 2048 wave slots at 32 instances per lane"}
+    res = {"workload": "2^20 instances, IV lengths {0,32,64,80}, 65536 bits each, row-major u32 + f32"}
+    legs = (("auto", mickey.SCHED_AUTO, mickey.TRANSPOSE_AUTO),
+            ("split_fused", mickey.SCHED_SPLIT, mickey.TRANSPOSE_FUSED),
+            ("one_wave_fused", mickey.SCHED_ONE_WAVE, mickey.TRANSPOSE_FUSED))
+    for name, sched, tp in legs:
+        m = mickey.Mickey(dk, dv, db, stream=stream)
+        m.set_schedule(sched)
+        m.set_transpose(tp)
+        m.generate_rowmajor(nbits, u, f)  # warm-up
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        t_init, t_gen = [], []
+        for _ in range(reps):
+            ev[0].record(stream)
+            m.rekey(dk, dv, db)
+            ev[1].record(stream)
+            m.generate_rowmajor(nbits, u, f)
+            ev[2].record(stream)
+            torch.cuda.synchronize()
+            t_init.append(ev[0].elapsed_time(ev[1]))
+            t_gen.append(ev[1].elapsed_time(ev[2]))
+        m.close()
+        ti, tg = float(np.mean(t_init)), float(np.mean(t_gen))
+        ops = mickey.ops_per_clock() * (n // 32) * nbits
+        print("# rowmajor-1m %s: init %.3f ms, generate %.3f ms" % (name, ti, tg), file=sys.stderr, flush=True)
+        leg = {"gbit_s": round(bits / ((ti + tg) * 1e-3) / 1e9, 3), "init_ms": round(ti, 4),
+               "generate_ms": round(tg, 4), "generate_gbit_s": round(bits / (tg * 1e-3) / 1e9, 3),
+               "valu_frac": round(ops / (tg * 1e-3) / (VALU_PEAK_TOPS * 1e12), 4)}
+        if name == "auto":
+            res.update(leg)
+            res["path"] = "split schedule (%d waves) into 8192-clock bit-plane chunks + tiled transpose" % (
+                2 * (n // 32 // 64))
+        else:
+            res[name] = leg
+    return res
 
 
 def bench_grain(torch, mickey, synth, reps: int = 5):

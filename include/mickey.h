@@ -114,6 +114,38 @@ int mickey_set_stream(mickey_state *st, void *hip_stream);
  * not depend on it. */
 int mickey_set_word_bits(mickey_state *st, int word_bits);
 
+/* Work split of the generate kernels (the output bytes do not depend on it):
+ *   MICKEY_SCHED_ONE_WAVE  one lane keeps all 200 state words of its slice(s);
+ *   MICKEY_SCHED_SPLIT     two waves per 64 slices, one keeping the R words and one the
+ *                          S words; every clock they exchange the bits that cross
+ *                          between the registers (r_33, s_34, s_0) through LDS.  Twice
+ *                          the waves for the same work: for calls too small to fill the
+ *                          device.  32-bit words only (MICKEY_EINVAL with word_bits 64,
+ *                          in either order of the two calls);
+ *   MICKEY_SCHED_AUTO      (default) SPLIT when word_bits is 32 and the one-wave launch
+ *                          has at most one wave per SIMD (n <= 2^21 on MI355X), else
+ *                          ONE_WAVE. */
+#define MICKEY_SCHED_AUTO 0
+#define MICKEY_SCHED_ONE_WAVE 1
+#define MICKEY_SCHED_SPLIT 2
+int mickey_set_schedule(mickey_state *st, int schedule);
+
+/* How the row-major layouts are produced (the output bytes do not depend on it):
+ *   MICKEY_TRANSPOSE_FUSED   inside the generate kernel: every 32 clocks each lane
+ *                            transposes its 32 x 32 block and stores one word per
+ *                            instance (4-byte stores spread over 64 rows per instruction);
+ *   MICKEY_TRANSPOSE_STAGED  the keystream goes to a library-owned bit-plane buffer in
+ *                            chunks of up to 8192 clocks (at most 512 MiB, allocated on
+ *                            first use, kept until mickey_free), and a tiled transpose
+ *                            kernel writes 1024-clock row segments as whole lines;
+ *   MICKEY_TRANSPOSE_AUTO    (default) STAGED unless one 1024-clock tile of planes
+ *                            exceeds 2 GiB (n > 2^24), then FUSED.
+ * A failed chunk-buffer allocation makes the generate call return MICKEY_ENOMEM. */
+#define MICKEY_TRANSPOSE_AUTO 0
+#define MICKEY_TRANSPOSE_FUSED 1
+#define MICKEY_TRANSPOSE_STAGED 2
+int mickey_set_transpose(mickey_state *st, int mode);
+
 size_t mickey_num_instances(const mickey_state *st);
 /* Keystream bits produced so far by each instance of the state. */
 uint64_t mickey_bits_generated(const mickey_state *st);

@@ -204,6 +204,60 @@ __device__ __forceinline__ void clock_gen(Regs<K> &x)
     clock_core<K, false>(x, fbr, fbs, fbr);
 }
 
+// ---------------------------------------------------------------------------------
+// Split keystream clock: one wave holds R, another holds S of the same instances, and
+// the two control bits cross between them (c_R needs s_34, c_S needs r_33).  Each half
+// is cut where the value the other wave needs for the next clock is final: R runs
+// r_99..r_33 (r_33 of the next state is then known), S runs s_1..s_34.
+constexpr int kRCut = 33, kSCut = 34;  // the taps of c_S = s_67 ^ r_33 and c_R = s_34 ^ r_67
+
+template <int K, int J0, int... J>
+__device__ __forceinline__ void r_range(Regs<K> &x, const Word<K> &cr, const Word<K> &fbr,
+                                        std::integer_sequence<int, J...>)
+{
+    (r_step<99 - (J0 + J), K>(x, cr, fbr), ...);
+}
+// r_99 .. r_{kRCut}
+template <int K>
+__device__ __forceinline__ void r_upper(Regs<K> &x, const Word<K> &cr, const Word<K> &fbr)
+{
+    r_range<K, 0>(x, cr, fbr, std::make_integer_sequence<int, 100 - kRCut>{});
+}
+// r_{kRCut-1} .. r_0
+template <int K>
+__device__ __forceinline__ void r_lower(Regs<K> &x, const Word<K> &cr, const Word<K> &fbr)
+{
+    r_range<K, 100 - kRCut>(x, cr, fbr, std::make_integer_sequence<int, kRCut>{});
+}
+
+template <int K, int I0, int... J>
+__device__ __forceinline__ void s_range(Regs<K> &x, Word<K> &prev, const Word<K> &fbs, const Word<K> &g0,
+                                        const Word<K> &g1, std::integer_sequence<int, J...>)
+{
+    (s_step<I0 + J, K, false>(x, prev, fbs, g0, g1, fbs), ...);
+}
+// s_1 .. s_{kSCut}; prev must hold the old s_0 on entry
+template <int K>
+__device__ __forceinline__ void s_lower(Regs<K> &x, Word<K> &prev, const Word<K> &fbs, const Word<K> &g0,
+                                        const Word<K> &g1)
+{
+    s_range<K, 1>(x, prev, fbs, g0, g1, std::make_integer_sequence<int, kSCut>{});
+}
+// s_{kSCut+1} .. s_98, then s_99 and s_0
+template <int K>
+__device__ __forceinline__ void s_upper(Regs<K> &x, Word<K> &prev, const Word<K> &fbs, const Word<K> &g0,
+                                        const Word<K> &g1)
+{
+    s_range<K, kSCut + 1>(x, prev, fbs, g0, g1, std::make_integer_sequence<int, 98 - kSCut>{});
+    Word<K> v = prev;
+    constexpr bool f0 = in_set(kFb0, 99), f1 = in_set(kFb1, 99);
+    if constexpr (f0 && f1) v = v ^ fbs;
+    else if constexpr (f0) v = v ^ g0;
+    else if constexpr (f1) v = v ^ g1;
+    x.s[99] = v;
+    x.s[0] = fbs;
+}
+
 // Initialisation clock: mixing on, input word `in` (one input bit per lane).
 template <int K, bool MASKED>
 __device__ __forceinline__ void clock_mix(Regs<K> &x, const Word<K> &in, const Word<K> &m)

@@ -219,22 +219,12 @@ __device__ __forceinline__ void store_state(const Regs<K> &x, uint32_t *state, s
     }
 }
 
-// a3 + a5: 32 keystream clocks of one slice, delivered as one 32-bit word per
-// instance: emit(l, w) receives w whose bit (31 - b) is keystream bit b of the block
-// for instance l.  The per-clock words are staged in LDS (column `col` of zbuf, one
-// 32-word column per lane) and transposed in two 16-row halves so that no more than 16
-// words are live next to the 200 state registers.
-template <int U, int NT, class Emit>
-__device__ __forceinline__ void rowmajor_block(Regs<1> &x, uint32_t (&zbuf)[32][NT], uint32_t col, Emit &&emit)
+// a5: the transposition of a staged 32-clock block: row 31-b of column `col` holds the
+// keystream word of clock b (bit l = instance l); emit(l, w) receives instance l's word,
+// whose bit (31 - b) is clock b.  Two 16-row halves keep at most 16 words live.
+template <int NT, class Emit>
+__device__ __forceinline__ void rowmajor_flush(uint32_t (&zbuf)[32][NT], uint32_t col, Emit &&emit)
 {
-    static_assert(32 % U == 0, "unroll must divide 32");
-    for (int b0 = 0; b0 < 32; b0 += U) {
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            zbuf[31 - (b0 + u)][col] = (x.r[0] ^ x.s[0]).w[0];  // row 31-b holds clock b
-            clock_gen<1>(x);
-        }
-    }
 #pragma unroll
     for (int h = 0; h < 32; h += 16) {
         uint32_t a[16];
@@ -251,6 +241,25 @@ __device__ __forceinline__ void rowmajor_block(Regs<1> &x, uint32_t (&zbuf)[32][
         emit(i, lo);
         emit(i + 16, hi);
     }
+}
+
+// a3 + a5: 32 keystream clocks of one slice, delivered as one 32-bit word per
+// instance: emit(l, w) receives w whose bit (31 - b) is keystream bit b of the block
+// for instance l.  The per-clock words are staged in LDS (column `col` of zbuf, one
+// 32-word column per lane) and transposed in two 16-row halves so that no more than 16
+// words are live next to the 200 state registers.
+template <int U, int NT, class Emit>
+__device__ __forceinline__ void rowmajor_block(Regs<1> &x, uint32_t (&zbuf)[32][NT], uint32_t col, Emit &&emit)
+{
+    static_assert(32 % U == 0, "unroll must divide 32");
+    for (int b0 = 0; b0 < 32; b0 += U) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            zbuf[31 - (b0 + u)][col] = (x.r[0] ^ x.s[0]).w[0];  // row 31-b holds clock b
+            clock_gen<1>(x);
+        }
+    }
+    rowmajor_flush(zbuf, col, emit);
 }
 
 }  // namespace mickey

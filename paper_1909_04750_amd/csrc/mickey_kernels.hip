@@ -26,6 +26,7 @@ using namespace mickey_host;
 namespace {
 
 constexpr int kUnroll = 4;  // clocks per loop iteration of the generate kernels
+constexpr int kSplitWaves = 2;  // waves per SIMD the split kernel is compiled for
 
 // ------------------------------------------------------------------------ kernels
 
@@ -119,6 +120,239 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     store_state<1>(x, state, pitch, voff);
 }
 
+// Split generate, for calls with too few slices to give every SIMD two waves: a
+// workgroup of two waves serves 64 slices, wave 0 holding the R words and wave 1 the S
+// words, so each clock is two half-clocks running side by side on two SIMDs.  Per
+// clock the waves swap what the other register's update needs, through a
+// double-buffered LDS slot and one barrier: R sends r_33 (for c_S), S sends s_34 (for
+// c_R) and s_0 (for the keystream bit z = r_0 ^ s_0, which the R wave forms and
+// delivers).  Each wave writes its value as soon as its own update has made it final
+// (R after r_99..r_33, S after s_1..s_34) and reads the other's after the barrier, so
+// the LDS round trip overlaps the rest of its half-clock.  The buffer a clock writes
+// is the one the clock after next reads again, so one barrier per clock suffices.
+// ROWMAJOR: 32-clock blocks staged in LDS and transposed as in gen_rowmajor_kernel
+// (nbits % 32 == 0); otherwise one bit-plane word per clock as in gen_bitsliced_kernel.
+struct SplitLds {
+    uint32_t r33[2][64];
+    uint32_t s34[2][64];
+    uint32_t s0[2][64];
+};
+
+// Barrier for LDS traffic only (output stores stay in flight).  The caller issues its
+// LDS reads right after it and then fences the scheduler, so that the reads go out
+// before the half-clock's ALU work rather than wherever the scheduler would put them.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One clock of the R wave; s34/s0 hold the current state's s_34 and s_0 and are replaced
+// by the next state's.  `ph` is the exchange buffer of the next state.
+__device__ __forceinline__ void split_r_clock(Regs<1> &x, Word<1> &s34, Word<1> &s0, SplitLds &xl,
+                                              uint32_t lane, int ph)
+{
+    const Word<1> cr = s34 ^ x.r[67];
+    const Word<1> fbr = x.r[99];
+    r_upper<1>(x, cr, fbr);
+    xl.r33[ph][lane] = x.r[kRCut].w[0];
+    lds_barrier();
+    s34.w[0] = xl.s34[ph][lane];
+    s0.w[0] = xl.s0[ph][lane];
+    __builtin_amdgcn_sched_barrier(0);
+    r_lower<1>(x, cr, fbr);
+    // The LDS round trip is hidden behind r_lower: keep the next clock's work from moving
+    // in front of the wait for it.
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" : "+v"(s34.w[0]), "+v"(s0.w[0]));
+}
+
+__device__ __forceinline__ void split_s_clock(Regs<1> &x, Word<1> &r33, SplitLds &xl, uint32_t lane, int ph)
+{
+    const Word<1> cs = x.s[67] ^ r33;
+    const Word<1> fbs = x.s[99];
+    const Word<1> g1 = fbs & cs;
+    const Word<1> g0 = fbs ^ g1;
+    Word<1> prev = x.s[0];
+    s_lower<1>(x, prev, fbs, g0, g1);
+    xl.s34[ph][lane] = x.s[kSCut].w[0];
+    xl.s0[ph][lane] = fbs.w[0];  // the next s_0
+    lds_barrier();
+    r33.w[0] = xl.r33[ph][lane];
+    __builtin_amdgcn_sched_barrier(0);
+    s_upper<1>(x, prev, fbs, g0, g1);
+    __builtin_amdgcn_sched_barrier(0);  // c_S of the next clock waits for r_33 only here
+}
+
+template <bool ROWMAJOR>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(kSplitWaves, kSplitWaves))) void
+gen_split_kernel(uint32_t *__restrict__ state, uint32_t nslices, uint32_t n, uint64_t nbits,
+                 uint32_t *__restrict__ out, uint32_t *__restrict__ out_u32, float *__restrict__ out_f32)
+{
+    __shared__ SplitLds xl;
+    __shared__ uint32_t zbuf[ROWMAJOR ? 32 : 1][64];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const uint32_t g = blockIdx.x * 64u + lane;
+    // Lanes past the last slice run a copy of the block's first slice (g0 < nslices):
+    // every word they store equals the one that slice's own lane stores at the same
+    // address in the same instruction, so no store needs a branch.
+    const uint32_t gs = g < nslices ? g : blockIdx.x * 64u;
+    const size_t pitch = (size_t)nslices * 4u;
+    const uint32_t voff = gs * 4u;
+    Regs<1> x;
+    if (wave == 0) {
+#pragma unroll
+        for (int j = 0; j < 100; j++) x.r[j] = ld_word<1>((const char *)state + (size_t)j * pitch + voff);
+        xl.r33[0][lane] = x.r[kRCut].w[0];
+        lds_barrier();
+        Word<1> s34 = {{xl.s34[0][lane]}}, s0 = {{xl.s0[0][lane]}};
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (ROWMAJOR) {
+            const uint64_t nwords = nbits / 32;
+            const uint32_t first = g * 32u;
+            const uint32_t valid = n > first ? (n - first < 32u ? n - first : 32u) : 0u;
+            uint32_t *ou = out_u32 ? out_u32 + (size_t)first * nwords : nullptr;
+            float *of = out_f32 ? out_f32 + (size_t)first * nwords : nullptr;
+            for (uint64_t j = 0; j < nwords; j++) {
+                for (int b0 = 0; b0 < 32; b0 += kUnroll) {
+#pragma unroll
+                    for (int u = 0; u < kUnroll; u++) {
+                        zbuf[31 - (b0 + u)][lane] = (x.r[0] ^ s0).w[0];  // row 31-b holds clock b
+                        split_r_clock(x, s34, s0, xl, lane, (u + 1) & 1);
+                    }
+                }
+                rowmajor_flush(zbuf, lane, [&](int l, uint32_t w) {
+                    if ((uint32_t)l < valid) {
+                        const size_t off = (size_t)l * nwords + j;
+                        if (ou) store_global(ou + off, w);
+                        if (of) store_global_f32(of + off, (float)(w >> 8) * 0x1p-24f);
+                    }
+                });
+            }
+        } else {
+            char *plane = (char *)out;  // wave-uniform
+            uint64_t t = 0;
+            for (; t + kUnroll <= nbits; t += kUnroll) {
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++) {
+                    store_plane<1>(plane, voff, x.r[0] ^ s0);
+                    plane += pitch;
+                    split_r_clock(x, s34, s0, xl, lane, (u + 1) & 1);
+                }
+            }
+            for (; t < nbits; t++) {
+                store_plane<1>(plane, voff, x.r[0] ^ s0);
+                plane += pitch;
+                split_r_clock(x, s34, s0, xl, lane, (int)((t + 1) & 1));
+            }
+        }
+        uint32_t v = voff;
+        asm volatile("" : "+v"(v));  // keep the load addresses from living across the loop
+#pragma unroll
+        for (int j = 0; j < 100; j++) st_word<1>((char *)state + (size_t)j * pitch + v, x.r[j]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 100; j++) x.s[j] = ld_word<1>((const char *)state + (size_t)(100 + j) * pitch + voff);
+        xl.s34[0][lane] = x.s[kSCut].w[0];
+        xl.s0[0][lane] = x.s[0].w[0];
+        lds_barrier();
+        Word<1> r33 = {{xl.r33[0][lane]}};
+        __builtin_amdgcn_sched_barrier(0);
+        // the same clock count and buffer sequence as the R wave (one barrier per clock);
+        // an even unroll lets the S words alternate between two register sets, no copies
+        uint64_t t = 0;
+        for (; t + kUnroll <= nbits; t += kUnroll) {
+#pragma unroll
+            for (int u = 0; u < kUnroll; u++) split_s_clock(x, r33, xl, lane, (u + 1) & 1);
+        }
+        for (; t < nbits; t++) split_s_clock(x, r33, xl, lane, (int)((t + 1) & 1));
+        uint32_t v = voff;
+        asm volatile("" : "+v"(v));
+#pragma unroll
+        for (int j = 0; j < 100; j++) st_word<1>((char *)state + (size_t)(100 + j) * pitch + v, x.s[j]);
+    }
+}
+
+// a5, staged: a chunk of bit-planes (as gen_*_kernel writes them) turned into row-major
+// words by a tiled transpose, so that every row segment goes out as whole 128-byte lines.
+// The fused delivery above stores one 4-byte word per instance every 32 clocks, i.e. 64
+// lines per store instruction, which the memory system serves at about 0.3 TB/s; here a
+// workgroup stages a tile of 16 slices (512 instances) x 1024 clocks (64 KiB) in LDS,
+// transposes each 32 x 32 bit block in registers, and writes each instance's 32 words of
+// the tile as one line (two lines per store instruction).
+constexpr int kTpSlices = 16;                          // slices per tile
+constexpr int kTpBlocks = 32;                          // 32-clock blocks per tile
+constexpr int kTpClocks = 32 * kTpBlocks;
+constexpr int kTpInStride = 32 * kTpSlices + 16;       // LDS words per block; the pad puts
+                                                       // adjacent blocks in other banks
+
+__global__ __launch_bounds__(256) void rowmajor_transpose_kernel(const uint32_t *__restrict__ planes,
+                                                                 uint32_t nslices, uint32_t nclocks, uint32_t n,
+                                                                 uint64_t nwords, uint64_t w0,
+                                                                 uint32_t *__restrict__ out_u32,
+                                                                 float *__restrict__ out_f32)
+{
+    __shared__ uint32_t lds[kTpBlocks * kTpInStride];
+    static_assert(32 * kTpSlices * kTpBlocks <= kTpBlocks * kTpInStride, "row staging reuses the tile");
+    const uint32_t tid = threadIdx.x;
+    const uint32_t s0 = blockIdx.x * kTpSlices;
+    const uint32_t t0 = blockIdx.y * kTpClocks;
+    const uint32_t nb = min((uint32_t)kTpBlocks, (nclocks - t0) / 32u);  // blocks in this tile
+    // Read: each lane loads a pair of slice words (nslices is even, so a pair is either
+    // wholly inside the planes or wholly past the end; those past it re-read the last
+    // pair and their instances are never written).  32 rows (one block) per pass.
+    {
+        const uint32_t pr = tid & 7u, b = tid >> 3;
+        uint32_t sp = s0 + 2u * pr;
+        if (sp >= nslices) sp = nslices - 2u;
+        const uint32_t *src = planes + (size_t)(t0 + b) * nslices + sp;
+        uint32_t *dst = lds + b * kTpSlices + 2u * pr;
+        for (uint32_t q = 0; q < nb; q++) {
+            const uint2 v = *(const uint2 *)(src + (size_t)q * 32u * nslices);
+            dst[q * kTpInStride] = v.x;
+            dst[q * kTpInStride + 1] = v.y;
+        }
+    }
+    __syncthreads();
+    // Transpose: item (slice s, block q); row 31-b of the item holds clock 32q+b, so the
+    // transposed word l is instance l's word with bit 31-b = clock b.
+    uint32_t a[2][32];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const uint32_t item = tid + 256u * h, s = item & 15u, q = item >> 4;
+        if (q < nb) {
+#pragma unroll
+            for (int b = 0; b < 32; b++) a[h][31 - b] = lds[q * kTpInStride + b * kTpSlices + s];
+            transpose32(a[h]);
+        }
+    }
+    __syncthreads();
+    // Rows: instance 32s+l of the tile is row i, its block-q word at column q ^ s.
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const uint32_t item = tid + 256u * h, s = item & 15u, q = item >> 4;
+        if (q < nb) {
+#pragma unroll
+            for (int l = 0; l < 32; l++) lds[(32u * s + l) * 32u + (q ^ s)] = a[h][l];
+        }
+    }
+    __syncthreads();
+    const uint32_t w = tid & 31u;
+    if (w < nb) {
+        for (uint32_t i = tid >> 5; i < 32u * kTpSlices; i += 8u) {
+            const uint32_t inst = 32u * s0 + i;
+            if (inst >= n) break;
+            const uint32_t v = lds[i * 32u + (w ^ (i >> 5))];
+            const size_t off = (size_t)inst * nwords + w0 + t0 / 32u + w;
+            if (out_u32) store_global(out_u32 + off, v);
+            if (out_f32) store_global_f32(out_f32 + off, (float)(v >> 8) * 0x1p-24f);
+        }
+    }
+}
+
 // State export: one thread per instance packs its 200 bits (r_0..r_99, s_0..s_99)
 // MSB first into 25 bytes.
 __global__ __launch_bounds__(256) void export_kernel(const uint32_t *__restrict__ state, uint32_t nslices,
@@ -175,7 +409,12 @@ struct mickey_state {
     hipStream_t stream;
     uint64_t bits;
     int word_bits;
+    int schedule;   // MICKEY_SCHED_*
+    int transpose;  // MICKEY_TRANSPOSE_*
+    int simds;      // SIMDs of the device (4 per compute unit)
     int device;
+    uint32_t *chunk = nullptr;  // device, bit-plane chunk of the staged row-major path
+    uint64_t chunk_clocks = 0;  // its capacity in clocks (0: not allocated yet)
 };
 
 namespace mickey_host {
@@ -265,6 +504,7 @@ void destroy(mickey_state *st)
     if (st->planes) (void)hipFree(st->planes);
     if (st->stage) (void)hipFree(st->stage);
     if (st->host_status) (void)hipHostFree(st->host_status);
+    if (st->chunk) (void)hipFree(st->chunk);
     delete st;
 }
 
@@ -289,7 +529,15 @@ mickey_state *init_impl(const uint8_t *keys, const uint8_t *ivs, const uint8_t *
     st->nslices = st->n_pad / 32;
     st->stream = stream;
     st->word_bits = 32;
+    st->schedule = MICKEY_SCHED_AUTO;
+    st->transpose = MICKEY_TRANSPOSE_AUTO;
     hipGetDevice(&st->device);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, st->device) != hipSuccess || cus <= 0) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    st->simds = 4 * cus;
     const size_t pitch = st->nslices * 4;
     const size_t stage_bytes = (size_t)(kInputPlanes + kMaskPlanes) * pitch + 256;
     if (hipMalloc(&st->planes, 200 * pitch) != hipSuccess || hipMalloc(&st->stage, stage_bytes) != hipSuccess ||
@@ -309,6 +557,86 @@ mickey_state *init_impl(const uint8_t *keys, const uint8_t *ivs, const uint8_t *
     return st;
 }
 
+// The split schedule doubles the waves of a call.  Measured on MI355X (1024 SIMDs), it
+// is faster up to one one-wave-schedule wave per SIMD (1.5x at 256 waves, 1.25x at
+// 1024 in the bit-plane layout) and slower from 1536 waves on, where its per-clock
+// exchange costs more than the extra waves gain.
+bool use_split(const mickey_state *st)
+{
+    if (st->schedule == MICKEY_SCHED_SPLIT) return true;
+    if (st->schedule == MICKEY_SCHED_ONE_WAVE || st->word_bits != 32) return false;
+    const size_t waves = (st->nslices + 63) / 64;
+    return waves <= (size_t)st->simds;
+}
+
+// Staged row-major delivery: clocks per chunk for a chunk buffer of at most 512 MiB, in
+// whole transpose tiles (1024 clocks) and at most 8192; 0 when even one tile of planes
+// would exceed 2 GiB (the fused path then serves MICKEY_TRANSPOSE_AUTO).
+uint64_t staged_chunk_clocks(const mickey_state *st)
+{
+    const uint64_t pitch = st->nslices * 4;
+    if ((uint64_t)kTpClocks * pitch > (2ull << 30)) return 0;
+    uint64_t c = ((512ull << 20) / pitch) / kTpClocks * kTpClocks;
+    if (c < (uint64_t)kTpClocks) c = kTpClocks;
+    if (c > 8192) c = 8192;
+    return c;
+}
+
+int launch_generate_planes(mickey_state *st, uint64_t nbits, uint32_t *out);
+
+int generate_staged(mickey_state *st, uint64_t nbits, uint32_t *out_u32, float *out_f32, uint64_t cc)
+{
+    const size_t pitch = st->nslices * 4;
+    const uint64_t want = nbits < cc ? (nbits + kTpClocks - 1) / kTpClocks * kTpClocks : cc;
+    if (st->chunk_clocks < want) {
+        if (st->chunk) {
+            (void)hipStreamSynchronize(st->stream);
+            (void)hipFree(st->chunk);
+            st->chunk = nullptr;
+            st->chunk_clocks = 0;
+        }
+        if (hipMalloc(&st->chunk, want * pitch) != hipSuccess) {
+            (void)hipGetLastError();
+            st->chunk = nullptr;
+            return fail(MICKEY_ENOMEM, "mickey_generate: cannot allocate the %llu-byte row-major chunk buffer",
+                        (unsigned long long)(want * pitch));
+        }
+        st->chunk_clocks = want;
+    }
+    const uint64_t nwords = nbits / 32;
+    for (uint64_t c0 = 0; c0 < nbits; c0 += st->chunk_clocks) {
+        const uint64_t nc = nbits - c0 < st->chunk_clocks ? nbits - c0 : st->chunk_clocks;
+        int rc = launch_generate_planes(st, nc, st->chunk);
+        if (rc != MICKEY_OK) return rc;
+        const dim3 grid((unsigned)((st->nslices + kTpSlices - 1) / kTpSlices),
+                        (unsigned)((nc + kTpClocks - 1) / kTpClocks));
+        hipLaunchKernelGGL(rowmajor_transpose_kernel, grid, dim3(256), 0, st->stream, st->chunk,
+                           (uint32_t)st->nslices, (uint32_t)nc, (uint32_t)st->n, nwords, c0 / 32, out_u32, out_f32);
+        rc = check_launch("rowmajor_transpose_kernel");
+        if (rc != MICKEY_OK) return rc;
+    }
+    return MICKEY_OK;
+}
+
+// nbits clocks of every instance as bit-planes (pitch nslices*4 bytes) to out.
+int launch_generate_planes(mickey_state *st, uint64_t nbits, uint32_t *out)
+{
+    const size_t pitch = st->nslices * 4;
+    const unsigned nblocks = (unsigned)((st->nslices + 63) / 64);
+    if (use_split(st)) {
+        hipLaunchKernelGGL(gen_split_kernel<false>, dim3(nblocks), dim3(128), 0, st->stream, st->planes,
+                           (uint32_t)st->nslices, (uint32_t)st->n, nbits, out, nullptr, nullptr);
+    } else if (st->word_bits == 32) {
+        hipLaunchKernelGGL(gen_bitsliced_kernel<1>, dim3(nblocks), dim3(64), 0, st->stream, st->planes,
+                           (uint32_t)st->nslices, (uint32_t)pitch, nbits, out);
+    } else {
+        const size_t ngroups = st->nslices / 2;
+        hipLaunchKernelGGL(gen_bitsliced_kernel<2>, dim3((unsigned)((ngroups + 63) / 64)), dim3(64), 0,
+                           st->stream, st->planes, (uint32_t)ngroups, (uint32_t)pitch, nbits, out);
+    }
+    return check_launch("gen_bitsliced_kernel");
+}
+
 int generate_impl(mickey_state *st, uint64_t nbits, int layout, void *out, uint32_t *out_u32, float *out_f32)
 {
     if (!st) return fail(MICKEY_EINVAL, "mickey_generate: NULL state");
@@ -316,27 +644,29 @@ int generate_impl(mickey_state *st, uint64_t nbits, int layout, void *out, uint3
     if (nbits > MICKEY_MAX_BITS_PER_IV || st->bits > MICKEY_MAX_BITS_PER_IV - nbits)
         return fail(MICKEY_ERANGE, "mickey_generate: %llu + %llu bits exceeds 2^40 per key/IV pair",
                     (unsigned long long)st->bits, (unsigned long long)nbits);
-    const size_t pitch = st->nslices * 4;
+    const bool split = use_split(st);
+    const unsigned nblocks = (unsigned)((st->nslices + 63) / 64);
     if (layout == MICKEY_BITSLICED) {
         if (!out) return fail(MICKEY_EINVAL, "mickey_generate: NULL output");
-        if (st->word_bits == 32) {
-            hipLaunchKernelGGL(gen_bitsliced_kernel<1>, dim3((unsigned)((st->nslices + 63) / 64)), dim3(64), 0,
-                               st->stream, st->planes, (uint32_t)st->nslices, (uint32_t)pitch, nbits,
-                               (uint32_t *)out);
-        } else {
-            const size_t ngroups = st->nslices / 2;
-            hipLaunchKernelGGL(gen_bitsliced_kernel<2>, dim3((unsigned)((ngroups + 63) / 64)), dim3(64), 0,
-                               st->stream, st->planes, (uint32_t)ngroups, (uint32_t)pitch, nbits,
-                               (uint32_t *)out);
-        }
-        int rc = check_launch("gen_bitsliced_kernel");
+        int rc = launch_generate_planes(st, nbits, (uint32_t *)out);
         if (rc != MICKEY_OK) return rc;
     } else {
         if (nbits % 32 != 0) return fail(MICKEY_EINVAL, "row-major layouts need nbits %% 32 == 0");
         if (!out_u32 && !out_f32) return fail(MICKEY_EINVAL, "mickey_generate: NULL output");
-        hipLaunchKernelGGL(gen_rowmajor_kernel, dim3((unsigned)((st->nslices + 63) / 64)), dim3(64), 0,
-                           st->stream, st->planes, (uint32_t)st->nslices, (uint32_t)st->n, nbits / 32, out_u32,
-                           out_f32);
+        const uint64_t cc = staged_chunk_clocks(st);
+        if (st->transpose == MICKEY_TRANSPOSE_STAGED || (st->transpose == MICKEY_TRANSPOSE_AUTO && cc)) {
+            int rc = generate_staged(st, nbits, out_u32, out_f32, cc ? cc : (uint64_t)kTpClocks);
+            if (rc != MICKEY_OK) return rc;
+            st->bits += nbits;
+            return ok();
+        }
+        if (split) {
+            hipLaunchKernelGGL(gen_split_kernel<true>, dim3(nblocks), dim3(128), 0, st->stream, st->planes,
+                               (uint32_t)st->nslices, (uint32_t)st->n, nbits, nullptr, out_u32, out_f32);
+        } else {
+            hipLaunchKernelGGL(gen_rowmajor_kernel, dim3(nblocks), dim3(64), 0, st->stream, st->planes,
+                               (uint32_t)st->nslices, (uint32_t)st->n, nbits / 32, out_u32, out_f32);
+        }
         int rc = check_launch("gen_rowmajor_kernel");
         if (rc != MICKEY_OK) return rc;
     }
@@ -401,7 +731,29 @@ int mickey_set_word_bits(mickey_state *st, int word_bits)
     if (!st) return fail(MICKEY_EINVAL, "mickey_set_word_bits: NULL state");
     if (word_bits != 32 && word_bits != 64)
         return fail(MICKEY_ENOSYS, "mickey_set_word_bits: %d-bit words are not supported", word_bits);
+    if (word_bits == 64 && st->schedule == MICKEY_SCHED_SPLIT)
+        return fail(MICKEY_EINVAL, "mickey_set_word_bits: the split schedule uses 32-bit words");
     st->word_bits = word_bits;
+    return ok();
+}
+
+int mickey_set_transpose(mickey_state *st, int mode)
+{
+    if (!st) return fail(MICKEY_EINVAL, "mickey_set_transpose: NULL state");
+    if (mode != MICKEY_TRANSPOSE_AUTO && mode != MICKEY_TRANSPOSE_FUSED && mode != MICKEY_TRANSPOSE_STAGED)
+        return fail(MICKEY_EINVAL, "mickey_set_transpose: unknown mode %d", mode);
+    st->transpose = mode;
+    return ok();
+}
+
+int mickey_set_schedule(mickey_state *st, int schedule)
+{
+    if (!st) return fail(MICKEY_EINVAL, "mickey_set_schedule: NULL state");
+    if (schedule != MICKEY_SCHED_AUTO && schedule != MICKEY_SCHED_ONE_WAVE && schedule != MICKEY_SCHED_SPLIT)
+        return fail(MICKEY_EINVAL, "mickey_set_schedule: unknown schedule %d", schedule);
+    if (schedule == MICKEY_SCHED_SPLIT && st->word_bits != 32)
+        return fail(MICKEY_EINVAL, "mickey_set_schedule: the split schedule uses 32-bit words");
+    st->schedule = schedule;
     return ok();
 }
 

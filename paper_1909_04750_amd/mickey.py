@@ -11,12 +11,14 @@ from .build import LIB_PATH
 
 OK, EINVAL, ENOMEM, EDEVICE, ERANGE, ENOSYS = 0, -1, -2, -3, -4, -5
 BITSLICED, ROWMAJOR_U32, ROWMAJOR_F32 = 0, 1, 2
+SCHED_AUTO, SCHED_ONE_WAVE, SCHED_SPLIT = 0, 1, 2
+TRANSPOSE_AUTO, TRANSPOSE_FUSED, TRANSPOSE_STAGED = 0, 1, 2
 MAX_BITS_PER_IV = 1 << 40
 PACKED_STATE_BYTES = 25
 
 EXPORTED = [
     "mickey_init", "mickey_init_on_stream", "mickey_rekey", "mickey_generate", "mickey_generate_rowmajor",
-    "mickey_free", "mickey_set_stream", "mickey_set_word_bits", "mickey_num_instances",
+    "mickey_free", "mickey_set_stream", "mickey_set_word_bits", "mickey_set_schedule", "mickey_set_transpose", "mickey_num_instances",
     "mickey_bits_generated", "mickey_plane_pitch", "mickey_state_export", "mickey_state_import",
     "mickey_sync", "mickey_last_error", "mickey_last_error_message", "mickey_ops_per_clock",
     "mickey_batch_create", "mickey_batch_set", "mickey_batch_run", "mickey_batch_sync", "mickey_batch_stream",
@@ -71,6 +73,10 @@ def load_library():
     L.mickey_set_stream.restype = i
     L.mickey_set_word_bits.argtypes = [vp, i]
     L.mickey_set_word_bits.restype = i
+    L.mickey_set_schedule.argtypes = [vp, i]
+    L.mickey_set_schedule.restype = i
+    L.mickey_set_transpose.argtypes = [vp, i]
+    L.mickey_set_transpose.restype = i
     L.mickey_num_instances.argtypes = [vp]
     L.mickey_num_instances.restype = sz
     L.mickey_bits_generated.argtypes = [vp]
@@ -265,6 +271,14 @@ class Mickey:
 
     def set_word_bits(self, bits: int) -> None:
         _check(load_library().mickey_set_word_bits(self._h, int(bits)))
+
+    def set_schedule(self, schedule: int) -> None:
+        """SCHED_AUTO, SCHED_ONE_WAVE or SCHED_SPLIT (mickey_set_schedule)."""
+        _check(load_library().mickey_set_schedule(self._h, int(schedule)))
+
+    def set_transpose(self, mode: int) -> None:
+        """TRANSPOSE_AUTO, TRANSPOSE_FUSED or TRANSPOSE_STAGED (mickey_set_transpose)."""
+        _check(load_library().mickey_set_transpose(self._h, int(mode)))
 
     def set_stream(self, stream) -> None:
         _check(load_library().mickey_set_stream(self._h, _stream_handle(stream)))

@@ -24,10 +24,14 @@ def make(keys, ivs, ivb=None):
     return mickey.Mickey(to_dev(keys), to_dev(ivs), None if ivb is None else to_dev(ivb))
 
 
-def gpu_bitsliced(keys, ivs, ivb, nbits, word_bits=32):
+SCHEDULES = [mickey.SCHED_ONE_WAVE, mickey.SCHED_SPLIT]
+
+
+def gpu_bitsliced(keys, ivs, ivb, nbits, word_bits=32, schedule=mickey.SCHED_AUTO):
     m = make(keys, ivs, ivb)
     if word_bits != 32:
         m.set_word_bits(word_bits)
+    m.set_schedule(schedule)
     out = m.generate(nbits)
     torch.cuda.synchronize()
     planes = out.cpu().numpy().reshape(nbits, m.pitch)
@@ -84,10 +88,13 @@ def test_plain_1k_full_parity():
     assert bad[0].size == 0, "first mismatch at plane %d byte %d" % (bad[0][0], bad[1][0])
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("n,nbits", [(1, 1), (1, 37), (63, 130), (65, 257), (1000, 1003), (2113, 64)])
-def test_ragged_sizes_mixed_iv_lengths(n, nbits):
+def test_ragged_sizes_mixed_iv_lengths(n, nbits, schedule):
+    """Instance counts that leave lanes past the last slice (in the split schedule they
+    run a copy of another slice) and clock counts off the unrolled loop."""
     keys, ivs, ivb = random_inputs(n * 7 + nbits, n)
-    got = layouts.from_bitsliced(gpu_bitsliced(keys, ivs, ivb, nbits), n)
+    got = layouts.from_bitsliced(gpu_bitsliced(keys, ivs, ivb, nbits, schedule=schedule), n)
     want = oracle_bits(keys, ivs, ivb, nbits)
     assert (got == want).all()
 
@@ -119,10 +126,12 @@ def test_word64_matches_word32_bytes():
     assert a.tobytes() == b.tobytes()
 
 
-def test_split_generation_and_counter():
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_split_generation_and_counter(schedule):
     n = 300
     keys, ivs, ivb = random_inputs(4, n)
     m = make(keys, ivs, ivb)
+    m.set_schedule(schedule)
     parts = [m.generate(nb) for nb in (1, 31, 100, 500)]
     torch.cuda.synchronize()
     assert m.bits_generated == 632
@@ -159,9 +168,13 @@ def test_state_export_matches_oracle_and_resumes():
 
 
 @pytest.mark.parametrize("n,nbits", [(1, 32), (70, 96), (700, 1024)])
-def test_rowmajor_u32_f32(n, nbits):
+@pytest.mark.parametrize("transpose", [mickey.TRANSPOSE_FUSED, mickey.TRANSPOSE_STAGED])
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_rowmajor_u32_f32(n, nbits, schedule, transpose):
     keys, ivs, ivb = random_inputs(n + 1, n)
     m = make(keys, ivs, ivb)
+    m.set_schedule(schedule)
+    m.set_transpose(transpose)
     u, f = m.generate_rowmajor(nbits)
     torch.cuda.synchronize()
     want = layouts.to_rowmajor_u32(oracle_bits(keys, ivs, ivb, nbits))
@@ -176,6 +189,28 @@ def test_rowmajor_u32_f32(n, nbits):
     nxt = layouts.to_rowmajor_u32(oracle_bits(keys, ivs, ivb, 128, skip=nbits))
     assert (u2.cpu().numpy().view(np.uint32) == nxt[:, :2]).all()
     assert f2.cpu().numpy().tobytes() == layouts.u32_to_f32(nxt[:, 2:]).tobytes()
+    m.close()
+
+
+def test_staged_rowmajor_chunks_and_tiles():
+    """The staged path across several chunk-buffer loads (the buffer holds up to 8192
+    clocks here), a partial last transpose tile, a partial last slice tile (instance
+    counts off 512), and a later call that needs a larger buffer than the first."""
+    n = 600
+    keys, ivs, ivb = random_inputs(77, n)
+    m = make(keys, ivs, ivb)
+    m.set_transpose(mickey.TRANSPOSE_STAGED)
+    u1 = m.generate(96, mickey.ROWMAJOR_U32)                # buffer sized for one tile
+    u2, f2 = m.generate_rowmajor(8192 + 1024 + 96)          # grows it; two chunk loads
+    u3 = m.generate(2048 + 32, mickey.ROWMAJOR_U32)
+    torch.cuda.synchronize()
+    total = 96 + 9312 + 2080
+    want = layouts.to_rowmajor_u32(oracle_bits(keys, ivs, ivb, total))
+    assert (u1.cpu().numpy().view(np.uint32) == want[:, :3]).all()
+    assert (u2.cpu().numpy().view(np.uint32) == want[:, 3:3 + 291]).all()
+    assert f2.cpu().numpy().tobytes() == layouts.u32_to_f32(want[:, 3:3 + 291]).tobytes()
+    assert (u3.cpu().numpy().view(np.uint32) == want[:, 294:]).all()
+    assert m.bits_generated == total
     m.close()
 
 
@@ -196,6 +231,22 @@ def test_error_paths():
     with pytest.raises(mickey.MickeyError) as e:
         m.set_word_bits(16)
     assert e.value.code == mickey.ENOSYS
+    with pytest.raises(mickey.MickeyError) as e:
+        m.set_schedule(3)
+    assert e.value.code == mickey.EINVAL
+    with pytest.raises(mickey.MickeyError) as e:
+        m.set_transpose(3)
+    assert e.value.code == mickey.EINVAL
+    m.set_schedule(mickey.SCHED_SPLIT)  # the split schedule keeps 32-bit words
+    with pytest.raises(mickey.MickeyError) as e:
+        m.set_word_bits(64)
+    assert e.value.code == mickey.EINVAL
+    m.set_schedule(mickey.SCHED_AUTO)
+    m.set_word_bits(64)
+    with pytest.raises(mickey.MickeyError) as e:
+        m.set_schedule(mickey.SCHED_SPLIT)
+    assert e.value.code == mickey.EINVAL
+    m.set_word_bits(32)
     # the 2^40-bit budget per key/IV pair
     packed, _ = m.export_state()
     m.import_state(packed, mickey.MAX_BITS_PER_IV - 32)
@@ -216,7 +267,7 @@ def sample_indices(n, k, seed):
 def test_plain_4m_sampled_parity():
     """2^22 instances, 8192 bits, bitsliced, the launch configuration the benchmark times:
     all lanes of the first and last slice plus seeded random instances against the oracle;
-    word widths 32 and 64 must give identical bytes."""
+    word widths 32 and 64 and the split schedule must give identical bytes."""
     seed, n, nbits, _ = synth.workload("plain-4m")
     keys, ivs = synth.keys_ivs(seed, n)
     m = make(keys, ivs)
@@ -231,8 +282,13 @@ def test_plain_4m_sampled_parity():
     m2.set_word_bits(64)
     out2 = m2.generate(nbits)
     assert torch.equal(out, out2)
-    m.close()
     m2.close()
+    m3 = make(keys, ivs)
+    m3.set_schedule(mickey.SCHED_SPLIT)
+    out3 = m3.generate(nbits)
+    assert torch.equal(out, out3)
+    m.close()
+    m3.close()
 
 
 def test_rowmajor_1m_sampled_parity():
@@ -250,6 +306,38 @@ def test_rowmajor_1m_sampled_parity():
     assert (got_u == want).all()
     assert got_f.tobytes() == layouts.u32_to_f32(want).tobytes()
     m.close()
+    # the other schedule, and the fused transpose, give the same bytes for every instance
+    m2 = make(keys, ivs, ivb)
+    m2.set_schedule(mickey.SCHED_ONE_WAVE)
+    m2.set_transpose(mickey.TRANSPOSE_FUSED)
+    u2 = m2.generate(nbits, mickey.ROWMAJOR_U32)
+    assert torch.equal(u, u2)
+    m2.close()
+
+
+@pytest.mark.parametrize("n", [64 * 33, 64 * 1024 + 96])
+def test_schedules_agree_across_launch_shapes(n):
+    """Both schedules, every instance, a few hundred clocks: one call per layout and
+    a clock count that ends off the unrolled loop, at block counts that leave a
+    partial last workgroup (lanes past the last slice)."""
+    keys, ivs, ivb = random_inputs(n, n)
+    outs = []
+    for sched in SCHEDULES:
+        m = make(keys, ivs, ivb)
+        m.set_schedule(sched)
+        a = m.generate(203)
+        b = m.generate(96, mickey.ROWMAJOR_U32)
+        exp, bits = m.export_state()
+        outs.append((a, b, exp, bits))
+        m.close()
+    (a0, b0, e0, n0), (a1, b1, e1, n1) = outs
+    assert torch.equal(a0, a1) and torch.equal(b0, b1) and torch.equal(e0, e1) and n0 == n1 == 299
+    idx = sample_indices(n, 96, 9)
+    want = oracle_bits(keys[idx], ivs[idx], ivb[idx], 299)
+    ti = torch.from_numpy(idx).to(DEV)
+    got = layouts.from_bitsliced(a0.view(203, -1).cpu().numpy(), n)[idx]
+    assert (got == want[:, :203]).all()
+    assert (b0[ti].cpu().numpy().view(np.uint32) == layouts.to_rowmajor_u32(want[:, 203:])).all()
 
 
 def test_rekey_reuses_state():
