@@ -303,6 +303,19 @@ typedef struct mickey_chunk {
 } mickey_chunk;
 
 int mickey_server_set_chunk(mickey_server *s, uint64_t chunk_bytes);
+
+/* Kernels of the following quanta (the delivered bytes do not depend on them):
+ *   transpose  MICKEY_TRANSPOSE_FUSED: one kernel stores every lane's word per 32 clocks
+ *              into its request (one-wave schedule only); MICKEY_TRANSPOSE_STAGED: the
+ *              quantum writes bit-planes to a server-owned buffer (at most 512 MiB, made
+ *              at creation; a quantum whose planes exceed it runs as several launches)
+ *              and a tiled transpose writes each request's words as whole lines;
+ *              MICKEY_TRANSPOSE_AUTO: STAGED when the buffer exists (it does unless one
+ *              32-clock launch of planes exceeds 512 MiB).
+ *   schedule   for staged quanta, MICKEY_SCHED_ONE_WAVE / _SPLIT / _AUTO as for
+ *              mickey_set_schedule (AUTO: split up to one one-wave wave per SIMD).
+ * MICKEY_EINVAL for FUSED with SPLIT, or STAGED / SPLIT without the buffer. */
+int mickey_server_set_kernel(mickey_server *s, int schedule, int transpose);
 int64_t mickey_server_poll_chunks(mickey_server *s, mickey_chunk *out, size_t cap);
 int mickey_server_release_chunks(mickey_server *s, const uint64_t *handles, size_t n);
 /* Copy the first nwords words of a delivered, not yet released chunk into dst (device);

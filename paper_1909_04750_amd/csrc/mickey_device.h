@@ -262,4 +262,130 @@ __device__ __forceinline__ void rowmajor_block(Regs<1> &x, uint32_t (&zbuf)[32][
     rowmajor_flush(zbuf, col, emit);
 }
 
+// ---------------------------------------------------------------------------------
+// Split clock on two waves of one workgroup (wave 0 keeps the R words, wave 1 the S
+// words of the same slices).  Each clock the waves swap r_33, s_34 and s_0 through a
+// double-buffered LDS slot with one LDS-only barrier: a wave writes its value as soon as
+// its half-clock has made it final and reads the other's right after the barrier, so the
+// round trip overlaps the rest of the half-clock.  The slot a clock writes is read again
+// only two clocks later, after another barrier.  Both waves must run the same number of
+// clocks (one barrier each).
+struct SplitLds {
+    uint32_t r33[2][64];
+    uint32_t s34[2][64];
+    uint32_t s0[2][64];
+};
+
+// Barrier for LDS traffic only (output stores stay in flight).  The caller issues its
+// LDS reads right after it and then fences the scheduler, so that the reads go out
+// before the half-clock's ALU work rather than wherever the scheduler would put them.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One clock of the R wave; s34/s0 hold the current state's s_34 and s_0 and are replaced
+// by the next state's.  `ph` is the exchange buffer of the next state.
+__device__ __forceinline__ void split_r_clock(Regs<1> &x, Word<1> &s34, Word<1> &s0, SplitLds &xl,
+                                              uint32_t lane, int ph)
+{
+    const Word<1> cr = s34 ^ x.r[67];
+    const Word<1> fbr = x.r[99];
+    r_upper<1>(x, cr, fbr);
+    xl.r33[ph][lane] = x.r[kRCut].w[0];
+    lds_barrier();
+    s34.w[0] = xl.s34[ph][lane];
+    s0.w[0] = xl.s0[ph][lane];
+    __builtin_amdgcn_sched_barrier(0);
+    r_lower<1>(x, cr, fbr);
+    // The LDS round trip is hidden behind r_lower: keep the next clock's work from moving
+    // in front of the wait for it.
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" : "+v"(s34.w[0]), "+v"(s0.w[0]));
+}
+
+__device__ __forceinline__ void split_s_clock(Regs<1> &x, Word<1> &r33, SplitLds &xl, uint32_t lane, int ph)
+{
+    const Word<1> cs = x.s[67] ^ r33;
+    const Word<1> fbs = x.s[99];
+    const Word<1> g1 = fbs & cs;
+    const Word<1> g0 = fbs ^ g1;
+    Word<1> prev = x.s[0];
+    s_lower<1>(x, prev, fbs, g0, g1);
+    xl.s34[ph][lane] = x.s[kSCut].w[0];
+    xl.s0[ph][lane] = fbs.w[0];  // the next s_0
+    lds_barrier();
+    r33.w[0] = xl.r33[ph][lane];
+    __builtin_amdgcn_sched_barrier(0);
+    s_upper<1>(x, prev, fbs, g0, g1);
+    __builtin_amdgcn_sched_barrier(0);  // c_S of the next clock waits for r_33 only here
+}
+
+// ---------------------------------------------------------------------------------
+// a5, staged: tiled transpose of bit-planes (plane t: one word per slice, nslices words)
+// into per-instance row words.  A 256-thread workgroup takes a tile of kTpSlices slices
+// (512 instances) x kTpClocks clocks: it reads the tile's plane words into LDS, turns
+// every (slice, 32-clock block) pair into 32 row words with an in-register 32x32
+// transpose, and leaves row i (instance 32*s0 + i) of the tile in LDS, its block-q word
+// at tile_row_word(lds, i, q): bit 31 - b is clock t0 + 32q + b.
+constexpr int kTpSlices = 16;                     // slices per tile
+constexpr int kTpBlocks = 32;                     // 32-clock blocks per tile
+constexpr int kTpClocks = 32 * kTpBlocks;
+constexpr int kTpInStride = 32 * kTpSlices + 16;  // LDS words per block; the pad puts
+                                                  // adjacent blocks in other banks
+constexpr int kTpLdsWords = kTpBlocks * kTpInStride;
+static_assert(32 * kTpSlices * kTpBlocks <= kTpLdsWords, "row staging reuses the tile");
+
+// nb (<= kTpBlocks) blocks from clock t0, slices s0 .. s0+15 (those past nslices read a
+// copy of the last pair and must not be written out; nslices is even).  Ends with the
+// rows in LDS after a barrier.
+__device__ __forceinline__ void tile_to_rows(uint32_t *lds, const uint32_t *__restrict__ planes, uint32_t nslices,
+                                             uint32_t s0, uint32_t t0, uint32_t nb, uint32_t tid)
+{
+    {  // each lane loads a pair of slice words of one plane; 32 planes (one block) per pass
+        const uint32_t pr = tid & 7u, b = tid >> 3;
+        uint32_t sp = s0 + 2u * pr;
+        if (sp >= nslices) sp = nslices - 2u;
+        const uint32_t *src = planes + (size_t)(t0 + b) * nslices + sp;
+        uint32_t *dst = lds + b * kTpSlices + 2u * pr;
+        for (uint32_t q = 0; q < nb; q++) {
+            const uint2 v = *(const uint2 *)(src + (size_t)q * 32u * nslices);
+            dst[q * kTpInStride] = v.x;
+            dst[q * kTpInStride + 1] = v.y;
+        }
+    }
+    __syncthreads();
+    // item (slice s, block q): row 31-b holds clock 32q+b, so the transposed word l is
+    // instance l's word with bit 31-b = clock b
+    uint32_t a[2][32];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const uint32_t item = tid + 256u * h, s = item & 15u, q = item >> 4;
+        if (q < nb) {
+#pragma unroll
+            for (int b = 0; b < 32; b++) a[h][31 - b] = lds[q * kTpInStride + b * kTpSlices + s];
+            transpose32(a[h]);
+        }
+    }
+    __syncthreads();
+    // row 32s+l, block q at column q ^ s (the swizzle spreads a row's readers over banks)
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const uint32_t item = tid + 256u * h, s = item & 15u, q = item >> 4;
+        if (q < nb) {
+#pragma unroll
+            for (int l = 0; l < 32; l++) lds[(32u * s + l) * 32u + (q ^ s)] = a[h][l];
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t tile_row_word(const uint32_t *lds, uint32_t i, uint32_t q)
+{
+    return lds[i * 32u + (q ^ (i >> 5))];
+}
+
 }  // namespace mickey

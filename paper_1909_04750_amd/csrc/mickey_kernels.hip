@@ -132,60 +132,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 // is the one the clock after next reads again, so one barrier per clock suffices.
 // ROWMAJOR: 32-clock blocks staged in LDS and transposed as in gen_rowmajor_kernel
 // (nbits % 32 == 0); otherwise one bit-plane word per clock as in gen_bitsliced_kernel.
-struct SplitLds {
-    uint32_t r33[2][64];
-    uint32_t s34[2][64];
-    uint32_t s0[2][64];
-};
-
-// Barrier for LDS traffic only (output stores stay in flight).  The caller issues its
-// LDS reads right after it and then fences the scheduler, so that the reads go out
-// before the half-clock's ALU work rather than wherever the scheduler would put them.
-__device__ __forceinline__ void lds_barrier()
-{
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// One clock of the R wave; s34/s0 hold the current state's s_34 and s_0 and are replaced
-// by the next state's.  `ph` is the exchange buffer of the next state.
-__device__ __forceinline__ void split_r_clock(Regs<1> &x, Word<1> &s34, Word<1> &s0, SplitLds &xl,
-                                              uint32_t lane, int ph)
-{
-    const Word<1> cr = s34 ^ x.r[67];
-    const Word<1> fbr = x.r[99];
-    r_upper<1>(x, cr, fbr);
-    xl.r33[ph][lane] = x.r[kRCut].w[0];
-    lds_barrier();
-    s34.w[0] = xl.s34[ph][lane];
-    s0.w[0] = xl.s0[ph][lane];
-    __builtin_amdgcn_sched_barrier(0);
-    r_lower<1>(x, cr, fbr);
-    // The LDS round trip is hidden behind r_lower: keep the next clock's work from moving
-    // in front of the wait for it.
-    __builtin_amdgcn_sched_barrier(0);
-    asm volatile("" : "+v"(s34.w[0]), "+v"(s0.w[0]));
-}
-
-__device__ __forceinline__ void split_s_clock(Regs<1> &x, Word<1> &r33, SplitLds &xl, uint32_t lane, int ph)
-{
-    const Word<1> cs = x.s[67] ^ r33;
-    const Word<1> fbs = x.s[99];
-    const Word<1> g1 = fbs & cs;
-    const Word<1> g0 = fbs ^ g1;
-    Word<1> prev = x.s[0];
-    s_lower<1>(x, prev, fbs, g0, g1);
-    xl.s34[ph][lane] = x.s[kSCut].w[0];
-    xl.s0[ph][lane] = fbs.w[0];  // the next s_0
-    lds_barrier();
-    r33.w[0] = xl.r33[ph][lane];
-    __builtin_amdgcn_sched_barrier(0);
-    s_upper<1>(x, prev, fbs, g0, g1);
-    __builtin_amdgcn_sched_barrier(0);  // c_S of the next clock waits for r_33 only here
-}
-
 template <bool ROWMAJOR>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(kSplitWaves, kSplitWaves))) void
 gen_split_kernel(uint32_t *__restrict__ state, uint32_t nslices, uint32_t n, uint64_t nbits,
@@ -276,76 +222,29 @@ gen_split_kernel(uint32_t *__restrict__ state, uint32_t nslices, uint32_t n, uin
     }
 }
 
-// a5, staged: a chunk of bit-planes (as gen_*_kernel writes them) turned into row-major
-// words by a tiled transpose, so that every row segment goes out as whole 128-byte lines.
-// The fused delivery above stores one 4-byte word per instance every 32 clocks, i.e. 64
-// lines per store instruction, which the memory system serves at about 0.3 TB/s; here a
-// workgroup stages a tile of 16 slices (512 instances) x 1024 clocks (64 KiB) in LDS,
-// transposes each 32 x 32 bit block in registers, and writes each instance's 32 words of
-// the tile as one line (two lines per store instruction).
-constexpr int kTpSlices = 16;                          // slices per tile
-constexpr int kTpBlocks = 32;                          // 32-clock blocks per tile
-constexpr int kTpClocks = 32 * kTpBlocks;
-constexpr int kTpInStride = 32 * kTpSlices + 16;       // LDS words per block; the pad puts
-                                                       // adjacent blocks in other banks
-
+// a5, staged: a chunk of bit-planes (as the generate kernels write them) turned into
+// row-major words by the tiled transpose of tile_to_rows, so that every row segment goes
+// out as whole 128-byte lines.  The fused delivery above stores one 4-byte word per
+// instance every 32 clocks, i.e. 64 lines per store instruction, which the memory system
+// serves at about 0.3 TB/s; here each store instruction writes two lines.
 __global__ __launch_bounds__(256) void rowmajor_transpose_kernel(const uint32_t *__restrict__ planes,
                                                                  uint32_t nslices, uint32_t nclocks, uint32_t n,
                                                                  uint64_t nwords, uint64_t w0,
                                                                  uint32_t *__restrict__ out_u32,
                                                                  float *__restrict__ out_f32)
 {
-    __shared__ uint32_t lds[kTpBlocks * kTpInStride];
-    static_assert(32 * kTpSlices * kTpBlocks <= kTpBlocks * kTpInStride, "row staging reuses the tile");
+    __shared__ uint32_t lds[kTpLdsWords];
     const uint32_t tid = threadIdx.x;
     const uint32_t s0 = blockIdx.x * kTpSlices;
     const uint32_t t0 = blockIdx.y * kTpClocks;
     const uint32_t nb = min((uint32_t)kTpBlocks, (nclocks - t0) / 32u);  // blocks in this tile
-    // Read: each lane loads a pair of slice words (nslices is even, so a pair is either
-    // wholly inside the planes or wholly past the end; those past it re-read the last
-    // pair and their instances are never written).  32 rows (one block) per pass.
-    {
-        const uint32_t pr = tid & 7u, b = tid >> 3;
-        uint32_t sp = s0 + 2u * pr;
-        if (sp >= nslices) sp = nslices - 2u;
-        const uint32_t *src = planes + (size_t)(t0 + b) * nslices + sp;
-        uint32_t *dst = lds + b * kTpSlices + 2u * pr;
-        for (uint32_t q = 0; q < nb; q++) {
-            const uint2 v = *(const uint2 *)(src + (size_t)q * 32u * nslices);
-            dst[q * kTpInStride] = v.x;
-            dst[q * kTpInStride + 1] = v.y;
-        }
-    }
-    __syncthreads();
-    // Transpose: item (slice s, block q); row 31-b of the item holds clock 32q+b, so the
-    // transposed word l is instance l's word with bit 31-b = clock b.
-    uint32_t a[2][32];
-#pragma unroll
-    for (int h = 0; h < 2; h++) {
-        const uint32_t item = tid + 256u * h, s = item & 15u, q = item >> 4;
-        if (q < nb) {
-#pragma unroll
-            for (int b = 0; b < 32; b++) a[h][31 - b] = lds[q * kTpInStride + b * kTpSlices + s];
-            transpose32(a[h]);
-        }
-    }
-    __syncthreads();
-    // Rows: instance 32s+l of the tile is row i, its block-q word at column q ^ s.
-#pragma unroll
-    for (int h = 0; h < 2; h++) {
-        const uint32_t item = tid + 256u * h, s = item & 15u, q = item >> 4;
-        if (q < nb) {
-#pragma unroll
-            for (int l = 0; l < 32; l++) lds[(32u * s + l) * 32u + (q ^ s)] = a[h][l];
-        }
-    }
-    __syncthreads();
+    tile_to_rows(lds, planes, nslices, s0, t0, nb, tid);
     const uint32_t w = tid & 31u;
     if (w < nb) {
         for (uint32_t i = tid >> 5; i < 32u * kTpSlices; i += 8u) {
             const uint32_t inst = 32u * s0 + i;
             if (inst >= n) break;
-            const uint32_t v = lds[i * 32u + (w ^ (i >> 5))];
+            const uint32_t v = tile_row_word(lds, i, w);
             const size_t off = (size_t)inst * nwords + w0 + t0 / 32u + w;
             if (out_u32) store_global(out_u32 + off, v);
             if (out_f32) store_global_f32(out_f32 + off, (float)(v >> 8) * 0x1p-24f);

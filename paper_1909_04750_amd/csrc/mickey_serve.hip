@@ -73,8 +73,9 @@ __global__ __launch_bounds__(256) void admit_kernel(const Admit *__restrict__ ad
     atomicOr(fresh + (a.lane >> 5), 1u << (a.lane & 31u));
 }
 
-// Replace bit l of the 200 state words with the packed state at src (25 bytes, r_0..r_99
-// then s_0..s_99, most significant bit first).
+// Replace bit l of state words J0..J1-1 (0..99: r_j, 100..199: s_{j-100}) with the
+// packed state at src (25 bytes, r_0..r_99 then s_0..s_99, most significant bit first).
+template <int J0 = 0, int J1 = 200>
 __device__ __forceinline__ void gather_lane(Regs<1> &x, uint32_t l, const uint8_t *src)
 {
     uint32_t w[7];
@@ -82,13 +83,17 @@ __device__ __forceinline__ void gather_lane(Regs<1> &x, uint32_t l, const uint8_
     for (int k = 0; k < 7; k++) {
         uint32_t v = 0;
 #pragma unroll
-        for (int b = 0; b < 4; b++) v = (v << 8) | (4 * k + b < 25 ? (uint32_t)src[4 * k + b] : 0u);
+        for (int b = 0; b < 4; b++) {
+            const int byte = 4 * k + b;
+            const bool used = byte < 25 && byte * 8 + 7 >= J0 && byte * 8 < J1;
+            v = (v << 8) | (used ? (uint32_t)src[byte] : 0u);
+        }
         w[k] = v;
     }
     const uint32_t m = 1u << l;
     constexpr int kSel = (TA & ~TB & 0xFF) | (TC & TB);  // b ? c : a
 #pragma unroll
-    for (int j = 0; j < 200; j++) {
+    for (int j = J0; j < J1; j++) {
         const uint32_t bit = 0u - ((w[j >> 5] >> (31 - (j & 31))) & 1u);
         Word<1> &dst = j < 100 ? x.r[j] : x.s[j - 100];
         dst.w[0] = __builtin_amdgcn_bitop3_b32(dst.w[0], m, bit, kSel);
@@ -108,6 +113,33 @@ __device__ __forceinline__ void write_back_lane(const Regs<1> &x, uint32_t l, ui
     }
 #pragma unroll
     for (int b = 0; b < 25; b++) dst[b] = (uint8_t)(w[b >> 2] >> (24 - 8 * (b & 3)));
+}
+
+// Half of write_back_lane, for the split schedule where one wave holds R and another S:
+// R is bytes 0..11 and the high nibble of byte 12, S the low nibble of byte 12 and bytes
+// 13..24.  The shared byte is updated with two atomics on its aligned word, touching
+// only this half's nibble (the other wave and the neighbouring states own the rest).
+template <bool R>
+__device__ __forceinline__ void write_back_half(const Regs<1> &x, uint32_t l, uint8_t *dst)
+{
+    constexpr int J0 = R ? 0 : 100;
+    uint32_t w[7];
+#pragma unroll
+    for (int k = 0; k < 7; k++) w[k] = 0u;
+#pragma unroll
+    for (int j = J0; j < J0 + 100; j++) {
+        const uint32_t v = j < 100 ? x.r[j].w[0] : x.s[j - 100].w[0];
+        w[j >> 5] |= ((v >> l) & 1u) << (31 - (j & 31));
+    }
+#pragma unroll
+    for (int b = R ? 0 : 13; b < (R ? 12 : 25); b++) dst[b] = (uint8_t)(w[b >> 2] >> (24 - 8 * (b & 3)));
+    const uint32_t mask = R ? 0xF0u : 0x0Fu;
+    const uint32_t v12 = (w[3] >> 24) & mask;
+    const uintptr_t a = (uintptr_t)(dst + 12);
+    uint32_t *word = (uint32_t *)(a & ~(uintptr_t)3);
+    const uint32_t sh = (uint32_t)(a & 3u) * 8u;
+    atomicAnd(word, ~(mask << sh));
+    atomicOr(word, v12 << sh);
 }
 
 // One quantum of nblocks*32 clocks on every slice with an occupied lane bit.  Each lane's
@@ -274,6 +306,13 @@ struct mickey_server {
     uint32_t *lane_left = nullptr, *lane_sid = nullptr;
     uint32_t *fresh = nullptr;  // per slice: lanes admitted since the last quantum
     uint32_t *sink = nullptr;   // per slice: target of stores by lanes without output
+    // staged quanta: keystream planes of one launch, and per lane what it wrote
+    uint32_t *zplanes = nullptr;
+    uint32_t **row_dst = nullptr;
+    uint32_t *row_cnt = nullptr;
+    uint32_t sub_blocks = 0;  // blocks per staged launch (0: staging not available)
+    int schedule = MICKEY_SCHED_AUTO, transpose = MICKEY_TRANSPOSE_AUTO;
+    int simds = 1024;
     uint32_t *done_list = nullptr, *done_count = nullptr;
     Admit *dadm = nullptr;
     uint32_t *arena = nullptr;
@@ -319,7 +358,7 @@ void destroy(mickey_server *s)
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (void *p : {(void *)s->pool, (void *)s->planes, (void *)s->lane_out, (void *)s->lane_left,
                     (void *)s->lane_sid, (void *)s->fresh, (void *)s->sink, (void *)s->done_list, (void *)s->dadm,
-                    (void *)s->arena})
+                    (void *)s->arena, (void *)s->zplanes, (void *)s->row_dst, (void *)s->row_cnt})
         if (p) (void)hipFree(p);
     if (s->hadm) (void)hipHostFree(s->hadm);
     if (s->hcount) (void)hipHostFree(s->hcount);
@@ -328,6 +367,237 @@ void destroy(mickey_server *s)
         if (e) (void)hipEventDestroy(e);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
+}
+
+// ---------------------------------------------------------------------------------
+// Staged quanta.  The quantum kernels below write the keystream as bit-planes (plane t:
+// one word per slice) to a chunk buffer, with coalesced stores, and record per lane the
+// output position and word count of the launch (row_dst, row_cnt); serve_transpose_kernel
+// then writes each lane's words to its request in whole lines.  A quantum may run as
+// several such launch pairs when its planes exceed the chunk buffer.
+
+// Per-lane end-of-launch bookkeeping shared by the staged kernels: what the launch wrote
+// for each lane (blk blocks ran) and where the lane continues.
+__device__ __forceinline__ void staged_advance(uint32_t g, uint32_t blk, uint32_t **lane_out, uint32_t *lane_left,
+                                               uint32_t **row_dst, uint32_t *row_cnt)
+{
+    for (int l = 0; l < 32; l++) {
+        const uint32_t i = g * 32u + l;
+        const uint32_t left = lane_left[i];
+        const uint32_t done = left < blk ? left : blk;
+        uint32_t *const out = lane_out[i];
+        row_dst[i] = out;
+        row_cnt[i] = done;
+        if (left) {
+            lane_left[i] = left - done;
+            lane_out[i] = out + done;
+        }
+    }
+}
+
+// Lanes with words left, and the earliest block count at which one of them ends.
+__device__ __forceinline__ uint32_t scan_lanes(const uint32_t *lane_left, uint32_t g, uint32_t &next_end)
+{
+    uint32_t active = 0;
+    next_end = 0xFFFFFFFFu;
+    for (int l = 0; l < 32; l++) {
+        const uint32_t left = lane_left[g * 32u + l];
+        active |= (left ? 1u : 0u) << l;
+        if (left && left < next_end) next_end = left;
+    }
+    return active;
+}
+
+// Lanes whose words end with block blk (blk + 1 == next_end); next_end moves on.
+__device__ __forceinline__ uint32_t ending_lanes(const uint32_t *lane_left, uint32_t g, uint32_t active,
+                                                 uint32_t blk, uint32_t &next_end)
+{
+    uint32_t finished = 0;
+    next_end = 0xFFFFFFFFu;
+    for (uint32_t l = 0; l < 32; l++) {
+        if (!((active >> l) & 1u)) continue;
+        const uint32_t left = lane_left[g * 32u + l];
+        if (left == blk + 1u)
+            finished |= 1u << l;
+        else if (left < next_end)
+            next_end = left;
+    }
+    return finished;
+}
+
+// One-wave staged quantum: the plain generate loop (one plane store per clock) plus the
+// lane bookkeeping of quantum_kernel.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void quantum_planes_kernel(
+    uint32_t *__restrict__ planes, uint32_t nslices, uint32_t nblocks, uint32_t **lane_out,
+    uint32_t *__restrict__ lane_left, const uint32_t *__restrict__ lane_sid, uint8_t *__restrict__ pool,
+    uint32_t *__restrict__ fresh, uint32_t *__restrict__ zplanes, uint32_t **row_dst, uint32_t *__restrict__ row_cnt,
+    uint32_t *__restrict__ done_list, uint32_t *__restrict__ done_count)
+{
+    const uint32_t g = blockIdx.x * 64u + threadIdx.x;  // nslices is a multiple of 64
+    uint32_t next_end;
+    uint32_t active = scan_lanes(lane_left, g, next_end);
+    if (!active) {
+        for (int l = 0; l < 32; l++) row_cnt[g * 32u + l] = 0u;
+        return;
+    }
+    const size_t pitch = (size_t)nslices * 4u;
+    const uint32_t voff = g * 4u;
+    Regs<1> x;
+    load_state<1>(x, planes, pitch, voff);
+    uint32_t fr = fresh[g];
+    if (fr) {
+        fresh[g] = 0u;
+        while (fr) {
+            const uint32_t l = (uint32_t)__builtin_ctz(fr);
+            fr &= fr - 1u;
+            gather_lane(x, l, pool + 25ull * lane_sid[g * 32u + l]);
+        }
+    }
+    char *plane = (char *)zplanes;  // wave-uniform
+    uint32_t blk = 0;
+    for (; blk < nblocks && active; blk++) {
+        for (int b0 = 0; b0 < 32; b0 += kServeUnroll) {
+#pragma unroll
+            for (int u = 0; u < kServeUnroll; u++) {
+                store_plane<1>(plane, voff, x.r[0] ^ x.s[0]);
+                plane += pitch;
+                clock_gen<1>(x);
+            }
+        }
+        if (blk + 1u == next_end) {
+            const uint32_t finished = ending_lanes(lane_left, g, active, blk, next_end);
+            for (uint32_t l = 0; l < 32; l++) {
+                if ((finished >> l) & 1u) {
+                    write_back_lane(x, l, pool + 25ull * lane_sid[g * 32u + l]);
+                    done_list[atomicAdd(done_count, 1u)] = g * 32u + l;
+                }
+            }
+            active &= ~finished;
+        }
+    }
+    store_state<1>(x, planes, pitch, voff);
+    staged_advance(g, blk, lane_out, lane_left, row_dst, row_cnt);
+}
+
+// Split staged quantum: the two-wave schedule of the plain path (wave 0: R words and the
+// keystream, wave 1: S words).  Both waves see the same lane_left values throughout (the
+// R wave changes them only after a final barrier), so they run the same blocks and the
+// same number of barriers; each packs its own half of a finished lane's state.
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) void quantum_split_kernel(
+    uint32_t *__restrict__ planes, uint32_t nslices, uint32_t nblocks, uint32_t **lane_out,
+    uint32_t *__restrict__ lane_left, const uint32_t *__restrict__ lane_sid, uint8_t *__restrict__ pool,
+    uint32_t *__restrict__ fresh, uint32_t *__restrict__ zplanes, uint32_t **row_dst, uint32_t *__restrict__ row_cnt,
+    uint32_t *__restrict__ done_list, uint32_t *__restrict__ done_count)
+{
+    __shared__ SplitLds xl;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t g = blockIdx.x * 64u + lane;  // nslices is a multiple of 64
+    uint32_t next_end;
+    uint32_t active = scan_lanes(lane_left, g, next_end);
+    if (!active) {  // both waves leave here, before any barrier
+        if (wave == 0)
+            for (int l = 0; l < 32; l++) row_cnt[g * 32u + l] = 0u;
+        return;
+    }
+    const size_t pitch = (size_t)nslices * 4u;
+    const uint32_t voff = g * 4u;
+    const uint32_t fr0 = fresh[g];
+    Regs<1> x;
+    uint32_t blk = 0;
+    if (wave == 0) {
+#pragma unroll
+        for (int j = 0; j < 100; j++) x.r[j] = ld_word<1>((const char *)planes + (size_t)j * pitch + voff);
+        for (uint32_t fr = fr0; fr; fr &= fr - 1u) {
+            const uint32_t l = (uint32_t)__builtin_ctz(fr);
+            gather_lane<0, 100>(x, l, pool + 25ull * lane_sid[g * 32u + l]);
+        }
+        xl.r33[0][lane] = x.r[kRCut].w[0];
+        lds_barrier();
+        Word<1> s34 = {{xl.s34[0][lane]}}, s0 = {{xl.s0[0][lane]}};
+        __builtin_amdgcn_sched_barrier(0);
+        if (fr0) fresh[g] = 0u;  // both waves have read it (before the barrier)
+        char *plane = (char *)zplanes;
+        for (; blk < nblocks && active; blk++) {
+            for (int b0 = 0; b0 < 32; b0 += kServeUnroll) {
+#pragma unroll
+                for (int u = 0; u < kServeUnroll; u++) {
+                    store_plane<1>(plane, voff, x.r[0] ^ s0);
+                    plane += pitch;
+                    split_r_clock(x, s34, s0, xl, lane, (u + 1) & 1);
+                }
+            }
+            if (blk + 1u == next_end) {
+                const uint32_t finished = ending_lanes(lane_left, g, active, blk, next_end);
+                for (uint32_t l = 0; l < 32; l++) {
+                    if ((finished >> l) & 1u) {
+                        write_back_half<true>(x, l, pool + 25ull * lane_sid[g * 32u + l]);
+                        done_list[atomicAdd(done_count, 1u)] = g * 32u + l;
+                    }
+                }
+                active &= ~finished;
+            }
+        }
+        lds_barrier();  // the S wave has read lane_left for the last time
+        uint32_t v = voff;
+        asm volatile("" : "+v"(v));
+#pragma unroll
+        for (int j = 0; j < 100; j++) st_word<1>((char *)planes + (size_t)j * pitch + v, x.r[j]);
+        staged_advance(g, blk, lane_out, lane_left, row_dst, row_cnt);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 100; j++) x.s[j] = ld_word<1>((const char *)planes + (size_t)(100 + j) * pitch + voff);
+        for (uint32_t fr = fr0; fr; fr &= fr - 1u) {
+            const uint32_t l = (uint32_t)__builtin_ctz(fr);
+            gather_lane<100, 200>(x, l, pool + 25ull * lane_sid[g * 32u + l]);
+        }
+        xl.s34[0][lane] = x.s[kSCut].w[0];
+        xl.s0[0][lane] = x.s[0].w[0];
+        lds_barrier();
+        Word<1> r33 = {{xl.r33[0][lane]}};
+        __builtin_amdgcn_sched_barrier(0);
+        for (; blk < nblocks && active; blk++) {
+            for (int b0 = 0; b0 < 32; b0 += kServeUnroll) {
+#pragma unroll
+                for (int u = 0; u < kServeUnroll; u++) split_s_clock(x, r33, xl, lane, (u + 1) & 1);
+            }
+            if (blk + 1u == next_end) {
+                const uint32_t finished = ending_lanes(lane_left, g, active, blk, next_end);
+                for (uint32_t l = 0; l < 32; l++)
+                    if ((finished >> l) & 1u) write_back_half<false>(x, l, pool + 25ull * lane_sid[g * 32u + l]);
+                active &= ~finished;
+            }
+        }
+        lds_barrier();
+        uint32_t v = voff;
+        asm volatile("" : "+v"(v));
+#pragma unroll
+        for (int j = 0; j < 100; j++) st_word<1>((char *)planes + (size_t)(100 + j) * pitch + v, x.s[j]);
+    }
+}
+
+// Rows of the staged quantum: lane i's row_cnt[i] words of the launch go to row_dst[i],
+// tiles of 16 slices x 1024 clocks as in the plain path's staged transpose.  Tiles whose
+// lanes have no word in the tile's clocks skip the plane reads.
+__global__ __launch_bounds__(256) void serve_transpose_kernel(const uint32_t *__restrict__ zplanes, uint32_t nslices,
+                                                              uint32_t nclocks, uint32_t *const *row_dst,
+                                                              const uint32_t *__restrict__ row_cnt)
+{
+    __shared__ uint32_t lds[kTpLdsWords];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t s0 = blockIdx.x * kTpSlices;
+    const uint32_t t0 = blockIdx.y * kTpClocks;
+    const uint32_t w0 = t0 / 32u;
+    const uint32_t nb = min((uint32_t)kTpBlocks, (nclocks - t0) / 32u);
+    const bool any = row_cnt[32u * s0 + tid] > w0 || row_cnt[32u * s0 + tid + 256u] > w0;
+    if (!__syncthreads_or(any)) return;
+    tile_to_rows(lds, zplanes, nslices, s0, t0, nb, tid);
+    const uint32_t w = tid & 31u;
+    for (uint32_t i = tid >> 5; i < 32u * kTpSlices; i += 8u) {
+        const uint32_t lane = 32u * s0 + i;
+        const uint32_t cnt = row_cnt[lane];
+        if (w0 + w < cnt && w < nb) store_global(row_dst[lane] + w0 + w, tile_row_word(lds, i, w));
+    }
 }
 
 // Clear the completion counter (a kernel, so that the sequence stays capturable).
@@ -511,7 +781,26 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
         return nullptr;
     }
     const size_t budget_words = budget_bytes / 4;
-    bool okm = hipMalloc(&s->pool, 25 * s->nstates) == hipSuccess &&
+    // Staged quanta: launches of up to 512 MiB of planes, in whole 1024-clock transpose
+    // tiles when a launch holds at least one.
+    {
+        const uint64_t plane_bytes = s->nslices * 4;
+        uint64_t sub = std::min<uint64_t>(quantum_clocks, (512ull << 20) / plane_bytes / 32 * 32);
+        if (sub >= 1024 && sub < quantum_clocks) sub = sub / 1024 * 1024;
+        s->sub_blocks = (uint32_t)(sub / 32);
+    }
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            s->simds = 4 * cus;
+        (void)hipGetLastError();
+    }
+    bool okm = (s->sub_blocks == 0 ||
+                (hipMalloc(&s->zplanes, (size_t)s->sub_blocks * 32 * s->nslices * 4) == hipSuccess &&
+                 hipMalloc(&s->row_dst, s->nlanes * sizeof(uint32_t *)) == hipSuccess &&
+                 hipMalloc(&s->row_cnt, s->nlanes * 4) == hipSuccess)) &&
+               hipMalloc(&s->pool, 25 * s->nstates) == hipSuccess &&
                hipMalloc(&s->planes, 200 * s->nslices * 4) == hipSuccess &&
                hipMalloc(&s->lane_out, s->nlanes * sizeof(uint32_t *)) == hipSuccess &&
                hipMalloc(&s->lane_left, s->nlanes * 4) == hipSuccess &&
@@ -592,6 +881,42 @@ int64_t mickey_server_submit(mickey_server *s, uint32_t state_id, uint64_t nbits
     return (int64_t)r.id;
 }
 
+// The quantum's kernels.  Staged (planes, then rows) unless staging is unavailable or
+// the fused path was asked for; within staged, the split schedule while the one-wave
+// kernel would have at most one wave per SIMD (the plain path's rule).
+int launch_quantum(mickey_server *s, int b)
+{
+    const bool staged = s->sub_blocks && s->transpose != MICKEY_TRANSPOSE_FUSED;
+    uint32_t *const list = s->hlist_dev + (size_t)b * s->nlanes;
+    if (!staged) {
+        hipLaunchKernelGGL(quantum_kernel, dim3((unsigned)(s->nslices / 64)), dim3(64), 0, s->stream, s->planes,
+                           (uint32_t)s->nslices, s->qblocks, s->lane_out, s->lane_left, s->lane_sid, s->pool,
+                           s->fresh, s->sink, list, s->done_count + b);
+        return check_launch("quantum_kernel");
+    }
+    const bool split = s->schedule == MICKEY_SCHED_SPLIT ||
+                       (s->schedule == MICKEY_SCHED_AUTO && s->nslices / 64 <= (size_t)s->simds);
+    for (uint32_t b0 = 0; b0 < s->qblocks; b0 += s->sub_blocks) {
+        const uint32_t nb = std::min(s->sub_blocks, s->qblocks - b0);
+        if (split)
+            hipLaunchKernelGGL(quantum_split_kernel, dim3((unsigned)(s->nslices / 64)), dim3(128), 0, s->stream,
+                               s->planes, (uint32_t)s->nslices, nb, s->lane_out, s->lane_left, s->lane_sid, s->pool,
+                               s->fresh, s->zplanes, s->row_dst, s->row_cnt, list, s->done_count + b);
+        else
+            hipLaunchKernelGGL(quantum_planes_kernel, dim3((unsigned)(s->nslices / 64)), dim3(64), 0, s->stream,
+                               s->planes, (uint32_t)s->nslices, nb, s->lane_out, s->lane_left, s->lane_sid, s->pool,
+                               s->fresh, s->zplanes, s->row_dst, s->row_cnt, list, s->done_count + b);
+        int rc = check_launch("quantum kernel");
+        if (rc != MICKEY_OK) return rc;
+        const dim3 grid((unsigned)(s->nslices / kTpSlices), (nb * 32 + kTpClocks - 1) / kTpClocks);
+        hipLaunchKernelGGL(serve_transpose_kernel, grid, dim3(256), 0, s->stream, s->zplanes, (uint32_t)s->nslices,
+                           nb * 32, s->row_dst, s->row_cnt);
+        rc = check_launch("serve_transpose_kernel");
+        if (rc != MICKEY_OK) return rc;
+    }
+    return MICKEY_OK;
+}
+
 int mickey_server_step(mickey_server *s)
 {
     if (!s) return fail(MICKEY_EINVAL, "mickey_server_step: NULL server");
@@ -613,10 +938,7 @@ int mickey_server_step(mickey_server *s)
         const int b = (int)(s->next_q & 1);
         hipLaunchKernelGGL(reset_count_kernel, dim3(1), dim3(64), 0, s->stream, s->done_count + b);
         s->launch_ns[b] = now_ns();
-        hipLaunchKernelGGL(quantum_kernel, dim3((unsigned)(s->nslices / 64)), dim3(64), 0, s->stream, s->planes,
-                           (uint32_t)s->nslices, s->qblocks, s->lane_out, s->lane_left, s->lane_sid, s->pool,
-                           s->fresh, s->sink, s->hlist_dev + (size_t)b * s->nlanes, s->done_count + b);
-        rc = check_launch("quantum_kernel");
+        rc = launch_quantum(s, b);
         if (rc != MICKEY_OK) return rc;
         if (hipMemcpyAsync(s->hcount + b, s->done_count + b, 4, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
             hipEventRecord(s->ev[b], s->stream) != hipSuccess)
@@ -775,6 +1097,24 @@ int mickey_server_copy(const mickey_server *s, uint64_t id, uint32_t *dst, uint6
     if (hipMemcpyAsync(dst, src, nwords * 4, hipMemcpyDeviceToDevice, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
         return check_launch("mickey_server_copy");
+    return ok();
+}
+
+int mickey_server_set_kernel(mickey_server *s, int schedule, int transpose)
+{
+    if (!s) return fail(MICKEY_EINVAL, "mickey_server_set_kernel: NULL server");
+    if (schedule != MICKEY_SCHED_AUTO && schedule != MICKEY_SCHED_ONE_WAVE && schedule != MICKEY_SCHED_SPLIT)
+        return fail(MICKEY_EINVAL, "mickey_server_set_kernel: unknown schedule %d", schedule);
+    if (transpose != MICKEY_TRANSPOSE_AUTO && transpose != MICKEY_TRANSPOSE_FUSED &&
+        transpose != MICKEY_TRANSPOSE_STAGED)
+        return fail(MICKEY_EINVAL, "mickey_server_set_kernel: unknown transpose mode %d", transpose);
+    if (transpose == MICKEY_TRANSPOSE_FUSED && schedule == MICKEY_SCHED_SPLIT)
+        return fail(MICKEY_EINVAL, "mickey_server_set_kernel: the fused kernel runs the one-wave schedule");
+    if (!s->sub_blocks && (transpose == MICKEY_TRANSPOSE_STAGED || schedule == MICKEY_SCHED_SPLIT))
+        return fail(MICKEY_EINVAL, "mickey_server_set_kernel: staging needs one 32-clock plane chunk per "
+                                   "launch within 512 MiB (too many slots)");
+    s->schedule = schedule;
+    s->transpose = transpose;
     return ok();
 }
 

@@ -29,7 +29,7 @@ EXPORTED = [
     "mickey_server_state", "mickey_server_stream", "mickey_server_free", "mickey_server_submit_many",
     "mickey_server_release_many", "mickey_server_times_many", "mickey_server_wait",
     "mickey_server_set_chunk", "mickey_server_poll_chunks", "mickey_server_release_chunks",
-    "mickey_server_copy_chunk",
+    "mickey_server_copy_chunk", "mickey_server_set_kernel",
     "grain_init", "grain_rekey", "grain_generate", "grain_generate_rowmajor", "grain_free", "grain_set_stream",
     "grain_num_instances", "grain_bits_generated", "grain_plane_pitch", "grain_state_export",
     "grain_state_import", "grain_sync", "grain_ops_per_clock",
@@ -146,6 +146,8 @@ def load_library():
     L.mickey_server_times_many.restype = i
     L.mickey_server_wait.argtypes = [vp]
     L.mickey_server_wait.restype = i
+    L.mickey_server_set_kernel.argtypes = [vp, i, i]
+    L.mickey_server_set_kernel.restype = i
     L.mickey_server_set_chunk.argtypes = [vp, u64]
     L.mickey_server_set_chunk.restype = i
     L.mickey_server_poll_chunks.argtypes = [vp, vp, sz]
@@ -441,6 +443,10 @@ class Server:
             raise MickeyError(L.mickey_last_error(), L.mickey_last_error_message().decode())
         self._h = ctypes.c_void_p(h)
         self.n = init.n
+
+    def set_kernel(self, schedule: int = SCHED_AUTO, transpose: int = TRANSPOSE_AUTO) -> None:
+        """Kernels of the following quanta (mickey_server_set_kernel)."""
+        _check(load_library().mickey_server_set_kernel(self._h, int(schedule), int(transpose)))
 
     def submit(self, state_id: int, nbits: int) -> int:
         r = load_library().mickey_server_submit(self._h, int(state_id), int(nbits))

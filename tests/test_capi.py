@@ -56,6 +56,7 @@ def test_null_state_is_rejected_without_gpu(lib):
     assert lib.mickey_set_word_bits(None, 32) == mickey.EINVAL
     assert lib.mickey_set_schedule(None, mickey.SCHED_SPLIT) == mickey.EINVAL
     assert lib.mickey_set_transpose(None, mickey.TRANSPOSE_STAGED) == mickey.EINVAL
+    assert lib.mickey_server_set_kernel(None, 0, 0) == mickey.EINVAL
     assert lib.mickey_num_instances(None) == 0
     lib.mickey_free(None)  # NULL-safe
     assert lib.grain_generate(None, 32, None, 0) == mickey.EINVAL

@@ -26,6 +26,19 @@ def make_pool(seed, n, mixed=True):
     return keys, ivs, ivb, init
 
 
+# (schedule, transpose) of the quantum kernels: the fused one-wave kernel, and the staged
+# kernels (bit-planes, then a tiled transpose into the requests) with each schedule
+KERNELS = [(mickey.SCHED_ONE_WAVE, mickey.TRANSPOSE_FUSED), (mickey.SCHED_ONE_WAVE, mickey.TRANSPOSE_STAGED),
+           (mickey.SCHED_SPLIT, mickey.TRANSPOSE_STAGED)]
+KERNEL_IDS = ["fused", "staged-one-wave", "staged-split"]
+
+
+def server(init, kernel, **kw):
+    srv = mickey.Server(init, **kw)
+    srv.set_kernel(*kernel)
+    return srv
+
+
 def drain(srv, max_steps=100000):
     done = []
     for _ in range(max_steps):
@@ -56,9 +69,10 @@ def oracle_history(keys, ivs, ivb, sid, lengths):
     return out
 
 
-def test_served_streams_continue_states():
+@pytest.mark.parametrize("kernel", KERNELS, ids=KERNEL_IDS)
+def test_served_streams_continue_states(kernel):
     keys, ivs, ivb, init = make_pool(1, 300)
-    srv = mickey.Server(init, nslices=64, quantum_clocks=64, budget_bytes=1 << 20)
+    srv = server(init, kernel, nslices=64, quantum_clocks=64, budget_bytes=1 << 20)
     init.close()
     rng = np.random.default_rng(2)
     sids = rng.integers(0, 300, 400)
@@ -82,9 +96,10 @@ def test_served_streams_continue_states():
     srv.close()
 
 
-def test_request_alone_equals_in_mix():
+@pytest.mark.parametrize("kernel", KERNELS, ids=KERNEL_IDS)
+def test_request_alone_equals_in_mix(kernel):
     keys, ivs, ivb, init = make_pool(3, 200)
-    srv = mickey.Server(init, nslices=64, quantum_clocks=96, budget_bytes=1 << 20)
+    srv = server(init, kernel, nslices=64, quantum_clocks=96, budget_bytes=1 << 20)
     rng = np.random.default_rng(4)
     sids = rng.permutation(200)[:150]  # first request on each state
     lengths = 32 * rng.integers(1, 60, 150)
@@ -93,7 +108,7 @@ def test_request_alone_equals_in_mix():
     mixed = {k: fetch(srv, ids[k], int(lengths[k])) for k in (0, 17, 149)}
     srv.close()
     for k, w in mixed.items():
-        alone = mickey.Server(init, nslices=64, quantum_clocks=96, budget_bytes=1 << 20)
+        alone = server(init, kernel, nslices=64, quantum_clocks=96, budget_bytes=1 << 20)
         rid = alone.submit(int(sids[k]), int(lengths[k]))
         drain(alone)
         assert (fetch(alone, rid, int(lengths[k])) == w).all(), k
@@ -152,10 +167,11 @@ def test_submit_errors_and_2p40_limit():
     srv.close()
 
 
-def test_chunked_delivery_continues_states_exactly():
+@pytest.mark.parametrize("kernel", KERNELS, ids=KERNEL_IDS)
+def test_chunked_delivery_continues_states_exactly(kernel):
     keys, ivs, ivb, init = make_pool(7, 120)
     # budget 4 KiB: far smaller than several requests below, which stream through it
-    srv = mickey.Server(init, nslices=64, quantum_clocks=64, budget_bytes=4096)
+    srv = server(init, kernel, nslices=64, quantum_clocks=64, budget_bytes=4096)
     init.close()
     rng = np.random.default_rng(8)
     plan = []  # (state, bits, chunk bytes)
@@ -245,4 +261,37 @@ def test_chunked_delivery_errors():
     with pytest.raises(mickey.MickeyError):
         srv.copy(rid, torch.empty(8, dtype=torch.int32, device="cuda"), 8)
     assert srv.times(rid)[2] > 0
+    srv.close()
+
+
+@pytest.mark.parametrize("schedule", [mickey.SCHED_ONE_WAVE, mickey.SCHED_SPLIT])
+def test_staged_quantum_in_several_launches(schedule):
+    """2^17 slices: one 1024-clock launch of planes fills the 512 MiB staging buffer, so a
+    quantum of 2144 clocks runs as launches of 1024, 1024 and 96 clocks; requests that end
+    inside each launch, and idle slices (their tiles are skipped), between busy ones."""
+    keys, ivs, ivb, init = make_pool(10, 300)
+    srv = mickey.Server(init, nslices=1 << 17, quantum_clocks=2144, budget_bytes=1 << 22)
+    srv.set_kernel(schedule, mickey.TRANSPOSE_STAGED)
+    init.close()
+    rng = np.random.default_rng(11)
+    sids = rng.permutation(300)[:200]
+    lengths = 32 * rng.integers(1, 200, 200)
+    lengths[:4] = [32 * 32, 32 * 33, 32 * 64, 32 * 67]  # ends at and next to launch edges
+    ids = [srv.submit(int(s), int(nb)) for s, nb in zip(sids, lengths)]
+    assert sorted(drain(srv)) == sorted(ids)
+    for k in list(range(8)) + list(range(190, 200)):
+        want = oracle_history(keys, ivs, ivb, int(sids[k]), [int(lengths[k])])[0]
+        assert (fetch(srv, ids[k], int(lengths[k])) == want).all(), k
+    srv.close()
+
+
+def test_set_kernel_errors():
+    keys, ivs, ivb, init = make_pool(12, 8, mixed=False)
+    srv = mickey.Server(init, nslices=64, quantum_clocks=32, budget_bytes=1 << 12)
+    init.close()
+    for sched, tp in ((3, mickey.TRANSPOSE_AUTO), (mickey.SCHED_AUTO, 3),
+                      (mickey.SCHED_SPLIT, mickey.TRANSPOSE_FUSED)):
+        with pytest.raises(mickey.MickeyError) as e:
+            srv.set_kernel(sched, tp)
+        assert e.value.code == mickey.EINVAL
     srv.close()
