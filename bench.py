@@ -112,8 +112,8 @@ def bench_rowmajor(torch, mickey, synth, reps: int = 3):
                "valu_frac": round(ops / (tg * 1e-3) / (VALU_PEAK_TOPS * 1e12), 4)}
         if name == "auto":
             res.update(leg)
-            res["path"] = "split schedule (%d waves) into 8192-clock bit-plane chunks + tiled transpose" % (
-                2 * (n // 32 // 64))
+            res["path"] = ("split schedule (%d waves) into 4096-clock bit-plane chunks (two 512 MiB buffers), "
+                           "tiled transpose on a second stream overlapping the next chunk" % (2 * (n // 32 // 64)))
         else:
             res[name] = leg
     return res

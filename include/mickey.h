@@ -134,10 +134,13 @@ int mickey_set_schedule(mickey_state *st, int schedule);
  *   MICKEY_TRANSPOSE_FUSED   inside the generate kernel: every 32 clocks each lane
  *                            transposes its 32 x 32 block and stores one word per
  *                            instance (4-byte stores spread over 64 rows per instruction);
- *   MICKEY_TRANSPOSE_STAGED  the keystream goes to a library-owned bit-plane buffer in
- *                            chunks of up to 8192 clocks (at most 512 MiB, allocated on
- *                            first use, kept until mickey_free), and a tiled transpose
- *                            kernel writes 1024-clock row segments as whole lines;
+ *   MICKEY_TRANSPOSE_STAGED  the keystream goes to library-owned bit-plane buffers in
+ *                            chunks of up to 8192 clocks (two buffers of at most 512 MiB,
+ *                            allocated on first use, kept until mickey_free), and a tiled
+ *                            transpose kernel writes 1024-clock row segments as whole
+ *                            lines.  The transposes run on a library-owned second stream,
+ *                            overlapping the next chunk; the call's work still completes
+ *                            in order on the state's stream (it waits for the last one);
  *   MICKEY_TRANSPOSE_AUTO    (default) STAGED unless one 1024-clock tile of planes
  *                            exceeds 2 GiB (n > 2^24), then FUSED.
  * A failed chunk-buffer allocation makes the generate call return MICKEY_ENOMEM. */

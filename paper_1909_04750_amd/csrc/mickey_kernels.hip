@@ -312,8 +312,10 @@ struct mickey_state {
     int transpose;  // MICKEY_TRANSPOSE_*
     int simds;      // SIMDs of the device (4 per compute unit)
     int device;
-    uint32_t *chunk = nullptr;  // device, bit-plane chunk of the staged row-major path
-    uint64_t chunk_clocks = 0;  // its capacity in clocks (0: not allocated yet)
+    uint32_t *chunk = nullptr;  // device, two bit-plane chunk buffers of the staged row-major path
+    uint64_t chunk_clocks = 0;  // capacity of each in clocks (0: not allocated yet)
+    hipStream_t side = nullptr;  // staged transposes run here, overlapping the next chunk
+    hipEvent_t ev_gen[2] = {nullptr, nullptr}, ev_tp[2] = {nullptr, nullptr};
 };
 
 namespace mickey_host {
@@ -403,7 +405,13 @@ void destroy(mickey_state *st)
     if (st->planes) (void)hipFree(st->planes);
     if (st->stage) (void)hipFree(st->stage);
     if (st->host_status) (void)hipHostFree(st->host_status);
+    if (st->side) (void)hipStreamSynchronize(st->side);
     if (st->chunk) (void)hipFree(st->chunk);
+    for (int b = 0; b < 2; b++) {
+        if (st->ev_gen[b]) (void)hipEventDestroy(st->ev_gen[b]);
+        if (st->ev_tp[b]) (void)hipEventDestroy(st->ev_tp[b]);
+    }
+    if (st->side) (void)hipStreamDestroy(st->side);
     delete st;
 }
 
@@ -468,7 +476,7 @@ bool use_split(const mickey_state *st)
     return waves <= (size_t)st->simds;
 }
 
-// Staged row-major delivery: clocks per chunk for a chunk buffer of at most 512 MiB, in
+// Staged row-major delivery: clocks per chunk for chunk buffers of at most 512 MiB each, in
 // whole transpose tiles (1024 clocks) and at most 8192; 0 when even one tile of planes
 // would exceed 2 GiB (the fused path then serves MICKEY_TRANSPOSE_AUTO).
 uint64_t staged_chunk_clocks(const mickey_state *st)
@@ -483,37 +491,65 @@ uint64_t staged_chunk_clocks(const mickey_state *st)
 
 int launch_generate_planes(mickey_state *st, uint64_t nbits, uint32_t *out);
 
+// Chunk k is generated on the state's stream into buffer k % 2 and transposed on the
+// side stream, so the transpose of chunk k (HBM-bound) overlaps the generation of chunk
+// k + 1 (VALU-bound) where the generate kernel leaves room on the CUs.  Events order each
+// transpose after its chunk, each chunk after the transpose that last read its buffer,
+// and the state's stream after the last transpose.
 int generate_staged(mickey_state *st, uint64_t nbits, uint32_t *out_u32, float *out_f32, uint64_t cc)
 {
     const size_t pitch = st->nslices * 4;
+    if (!st->side) {
+        bool okc = hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking) == hipSuccess;
+        for (int b = 0; b < 2 && okc; b++)
+            okc = hipEventCreateWithFlags(&st->ev_gen[b], hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&st->ev_tp[b], hipEventDisableTiming) == hipSuccess;
+        if (!okc) {
+            (void)hipGetLastError();
+            return fail(MICKEY_EDEVICE, "mickey_generate: cannot create the transpose stream or its events");
+        }
+    }
     const uint64_t want = nbits < cc ? (nbits + kTpClocks - 1) / kTpClocks * kTpClocks : cc;
     if (st->chunk_clocks < want) {
         if (st->chunk) {
             (void)hipStreamSynchronize(st->stream);
+            (void)hipStreamSynchronize(st->side);
             (void)hipFree(st->chunk);
             st->chunk = nullptr;
             st->chunk_clocks = 0;
         }
-        if (hipMalloc(&st->chunk, want * pitch) != hipSuccess) {
+        if (hipMalloc(&st->chunk, 2 * want * pitch) != hipSuccess) {
             (void)hipGetLastError();
             st->chunk = nullptr;
-            return fail(MICKEY_ENOMEM, "mickey_generate: cannot allocate the %llu-byte row-major chunk buffer",
-                        (unsigned long long)(want * pitch));
+            return fail(MICKEY_ENOMEM, "mickey_generate: cannot allocate the %llu-byte row-major chunk buffers",
+                        (unsigned long long)(2 * want * pitch));
         }
         st->chunk_clocks = want;
     }
     const uint64_t nwords = nbits / 32;
-    for (uint64_t c0 = 0; c0 < nbits; c0 += st->chunk_clocks) {
+    int last = 0;
+    uint64_t k = 0;
+    for (uint64_t c0 = 0; c0 < nbits; c0 += st->chunk_clocks, k++) {
+        const int b = (int)(k & 1);
+        uint32_t *buf = st->chunk + (size_t)b * st->chunk_clocks * st->nslices;
         const uint64_t nc = nbits - c0 < st->chunk_clocks ? nbits - c0 : st->chunk_clocks;
-        int rc = launch_generate_planes(st, nc, st->chunk);
+        if (k >= 2 && hipStreamWaitEvent(st->stream, st->ev_tp[b], 0) != hipSuccess)
+            return check_launch("hipStreamWaitEvent");
+        int rc = launch_generate_planes(st, nc, buf);
         if (rc != MICKEY_OK) return rc;
+        if (hipEventRecord(st->ev_gen[b], st->stream) != hipSuccess ||
+            hipStreamWaitEvent(st->side, st->ev_gen[b], 0) != hipSuccess)
+            return check_launch("hipEventRecord");
         const dim3 grid((unsigned)((st->nslices + kTpSlices - 1) / kTpSlices),
                         (unsigned)((nc + kTpClocks - 1) / kTpClocks));
-        hipLaunchKernelGGL(rowmajor_transpose_kernel, grid, dim3(256), 0, st->stream, st->chunk,
-                           (uint32_t)st->nslices, (uint32_t)nc, (uint32_t)st->n, nwords, c0 / 32, out_u32, out_f32);
+        hipLaunchKernelGGL(rowmajor_transpose_kernel, grid, dim3(256), 0, st->side, buf, (uint32_t)st->nslices,
+                           (uint32_t)nc, (uint32_t)st->n, nwords, c0 / 32, out_u32, out_f32);
         rc = check_launch("rowmajor_transpose_kernel");
         if (rc != MICKEY_OK) return rc;
+        if (hipEventRecord(st->ev_tp[b], st->side) != hipSuccess) return check_launch("hipEventRecord");
+        last = b;
     }
+    if (hipStreamWaitEvent(st->stream, st->ev_tp[last], 0) != hipSuccess) return check_launch("hipStreamWaitEvent");
     return MICKEY_OK;
 }
 
