@@ -11,7 +11,6 @@ state write-back.  Prints one JSON line (value = keystream Gbit/s of the whole s
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,21 +29,24 @@ VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("csrc/bitmatrix.h", "csrc/mickey_bitslice.h", "csrc/mickey_device.h", "csrc/mickey_kernels.hip"):
-        h.update(open(os.path.join(ROOT, "paper_1909_04750_amd", f), "rb").read())
-    return h.hexdigest()[:16]
+HEADLINE_SYMBOL = "_ZN12_GLOBAL__N_120gen_bitsliced_kernelILi1EEEvPjjjmS1_"  # gen_bitsliced_kernel<1>
+
+
+def kernel_code_hash() -> str:
+    """Hash of the headline kernel's machine code in the built library."""
+    from paper_1909_04750_amd import codeobj
+    from paper_1909_04750_amd.build import LIB_PATH
+    return codeobj.kernel_code_hash(LIB_PATH, HEADLINE_SYMBOL) or "missing"
 
 
 def traffic_record(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source; otherwise None."""
+    on the kernel's current machine code; otherwise None."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, WORKLOAD))
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("source_hash") != kernel_source_hash():
+    if rec.get("code_hash") != kernel_code_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -479,10 +481,10 @@ def main() -> int:
                     help="seconds the open-loop served run continues after the last arrival")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
-    ap.add_argument("--source-hash", action="store_true", help="print the kernel source hash and exit")
+    ap.add_argument("--code-hash", action="store_true", help="print the headline kernel's code hash and exit")
     args = ap.parse_args()
-    if args.source_hash:
-        print(kernel_source_hash())
+    if args.code_hash:
+        print(kernel_code_hash())
         return 0
     if args.copy_calib:
         import torch

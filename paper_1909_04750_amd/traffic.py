@@ -6,7 +6,8 @@ Usage (from the repository root, after the two counter runs named in the summary
 
 Each counter is summed per dispatch (KiB), averaged over the dispatches of the kernel,
 and scaled by bytes / counter of a plain copy kernel of known size (1 GiB read, 1 GiB
-written per launch).  The record carries the source hash that bench.py checks.
+written per launch).  The record carries the hash of the kernel's machine code in the built
+library, which bench.py checks.
 """
 from __future__ import annotations
 
@@ -50,8 +51,8 @@ def main() -> int:
     fetch = sum(f) / len(f) * 1024.0 * kf
     write = sum(w) / len(w) * 1024.0 * kw
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    h = subprocess.check_output([sys.executable, os.path.join(root, "bench.py"), "--source-hash"]).decode().strip()
-    rec = {"kernel": a.kernel, "source_hash": h, "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+    h = subprocess.check_output([sys.executable, os.path.join(root, "bench.py"), "--code-hash"]).decode().strip()
+    rec = {"kernel": a.kernel, "code_hash": h, "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "hbm_bytes_per_launch": fetch + write, "calibration_factor": {"fetch": kf, "write": kw},
            "dispatches": {"fetch": len(f), "write": len(w)}}
     json.dump(rec, open(a.out, "w"), indent=1)
