@@ -85,3 +85,16 @@ def test_chunk_record_layout_matches_binding(tmp_path):
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     dt = np.dtype(mickey.Server.CHUNK_DTYPE)
     assert got == [dt.itemsize] + [dt.fields[f][1] for f in dt.names]
+
+
+def test_headline_kernel_code_hash_is_found():
+    """The traffic record is keyed by the headline kernel's machine code: the hash must be
+    found in the built library, and differ between kernels."""
+    from paper_1909_04750_amd import codeobj
+    from paper_1909_04750_amd.build import LIB_PATH
+    objs = codeobj.device_code_objects(LIB_PATH)
+    assert len(objs) >= 5  # one per HIP source
+    h1 = codeobj.kernel_code_hash(LIB_PATH, "_ZN12_GLOBAL__N_120gen_bitsliced_kernelILi1EEEvPjjjmS1_")
+    h2 = codeobj.kernel_code_hash(LIB_PATH, "_ZN12_GLOBAL__N_120gen_bitsliced_kernelILi2EEEvPjjjmS1_")
+    assert h1 and h2 and h1 != h2 and len(h1) == 16
+    assert codeobj.kernel_code_hash(LIB_PATH, "no_such_kernel") is None
