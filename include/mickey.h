@@ -122,12 +122,17 @@ int mickey_set_word_bits(mickey_state *st, int word_bits);
  *                          the waves for the same work: for calls too small to fill the
  *                          device.  32-bit words only (MICKEY_EINVAL with word_bits 64,
  *                          in either order of the two calls);
- *   MICKEY_SCHED_AUTO      (default) SPLIT when word_bits is 32 and the one-wave launch
- *                          has at most one wave per SIMD (n <= 2^21 on MI355X), else
- *                          ONE_WAVE. */
+ *   MICKEY_SCHED_SPLIT4    four waves per 64 slices, each keeping half of R or half of
+ *                          S and computing first the values the others need (10 words
+ *                          exchanged per clock); 128 VGPRs per wave.  Bit-planes only:
+ *                          the fused row-major path runs SPLIT instead.  32-bit words only;
+ *   MICKEY_SCHED_AUTO      (default) SPLIT4 when word_bits is 32 and the one-wave launch
+ *                          would leave SIMDs with fewer than two waves (n < 2^22 on
+ *                          MI355X), else ONE_WAVE. */
 #define MICKEY_SCHED_AUTO 0
 #define MICKEY_SCHED_ONE_WAVE 1
 #define MICKEY_SCHED_SPLIT 2
+#define MICKEY_SCHED_SPLIT4 3
 int mickey_set_schedule(mickey_state *st, int schedule);
 
 /* How the row-major layouts are produced (the output bytes do not depend on it):

@@ -205,6 +205,46 @@ __device__ __forceinline__ void clock_gen(Regs<K> &x)
 }
 
 // ---------------------------------------------------------------------------------
+// Next value of one register position as a function of the current state (nothing is
+// overwritten): used where a clock is computed in an order other than the in-place
+// sweeps above (the four-wave split computes the positions other waves need first).
+template <int I, int K>
+__device__ __forceinline__ Word<K> r_next(const Regs<K> &x, const Word<K> &cr, const Word<K> &fbr)
+{
+    if constexpr (I == 0) {
+        return b3<TA ^ (TB & TC)>(fbr, cr, x.r[0]);
+    } else {
+        Word<K> v = b3<TA ^ (TB & TC)>(x.r[I - 1], cr, x.r[I]);
+        if constexpr (in_set(kRTaps, I)) v = v ^ fbr;
+        return v;
+    }
+}
+
+template <int I, int K>
+__device__ __forceinline__ Word<K> s_next(const Regs<K> &x, const Word<K> &fbs, const Word<K> &g0,
+                                          const Word<K> &g1)
+{
+    if constexpr (I == 0) {
+        return fbs;
+    } else {
+        Word<K> v;
+        if constexpr (I == 99) {
+            v = x.s[98];
+        } else {
+            constexpr int bb = in_set(kComp0, I) ? (TB ^ 0xFF) : TB;
+            constexpr int cc = in_set(kComp1, I) ? (TC ^ 0xFF) : TC;
+            constexpr int imm = (TA ^ (bb & cc)) & 0xFF;
+            v = b3<imm>(x.s[I - 1], x.s[I], x.s[I + 1]);
+        }
+        constexpr bool f0 = in_set(kFb0, I), f1 = in_set(kFb1, I);
+        if constexpr (f0 && f1) v = v ^ fbs;
+        else if constexpr (f0) v = v ^ g0;
+        else if constexpr (f1) v = v ^ g1;
+        return v;
+    }
+}
+
+// ---------------------------------------------------------------------------------
 // Split keystream clock: one wave holds R, another holds S of the same instances, and
 // the two control bits cross between them (c_R needs s_34, c_S needs r_33).  Each half
 // is cut where the value the other wave needs for the next clock is final: R runs

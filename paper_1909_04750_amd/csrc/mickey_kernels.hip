@@ -26,7 +26,8 @@ using namespace mickey_host;
 namespace {
 
 constexpr int kUnroll = 4;  // clocks per loop iteration of the generate kernels
-constexpr int kSplitWaves = 2;  // waves per SIMD the split kernel is compiled for
+constexpr int kSplitWaves = 2;   // waves per SIMD the split kernel is compiled for
+constexpr int kSplit4Waves = 4;  // ... and the four-wave split (128 VGPRs)
 
 // ------------------------------------------------------------------------ kernels
 
@@ -220,6 +221,245 @@ gen_split_kernel(uint32_t *__restrict__ state, uint32_t nslices, uint32_t n, uin
 #pragma unroll
         for (int j = 0; j < 100; j++) st_word<1>((char *)state + (size_t)(100 + j) * pitch + v, x.s[j]);
     }
+}
+
+// Four-wave split, for launches that the two-wave split still leaves at one wave per SIMD:
+// a workgroup of four waves serves 64 slices, wave 0 holding r_0..r_49 (and forming and
+// storing the keystream), wave 1 r_50..r_99, wave 2 s_0..s_49, wave 3 s_50..s_99.  Every
+// position's next value is a function of the current state (r_next / s_next), so each wave
+// first computes the values the others need for the next clock, writes them to a
+// double-buffered LDS slot, passes the clock's one barrier, issues its reads, and only
+// then computes the rest of its half-register: the barrier waits for a handful of
+// operations per wave and the LDS round trip hides behind the rest.  Exchanged per clock
+// (next-state values): r_49 (to wave 1), r_33 (to the S waves, for c_S), r_99 and r_67
+// (to wave 0, for fb_R and c_R), s_34 (to the R waves, for c_R), s_0 (to wave 0, for z),
+// s_49 (to wave 3), s_50, s_99 and s_67 (to wave 2).  ~75-92 VALU per wave per clock.
+enum : int { kX_R49, kX_R33, kX_R99, kX_R67, kX_S49, kX_S34, kX_S0, kX_S50, kX_S99, kX_S67, kXSlots };
+struct Split4Lds {
+    uint32_t v[2][kXSlots][64];
+};
+
+constexpr bool ex3(int i, int a, int b, int c) { return i == a || i == b || i == c; }
+
+// n.r[LO + j] for j < N, except positions A, B, C
+template <int LO, int A, int B, int C, int... J>
+__device__ __forceinline__ void r_next_range(Regs<1> &n, const Regs<1> &x, const Word<1> &cr, const Word<1> &fbr,
+                                             std::integer_sequence<int, J...>)
+{
+    ((ex3(LO + J, A, B, C) ? void() : void(n.r[LO + J] = r_next<LO + J, 1>(x, cr, fbr))), ...);
+}
+template <int LO, int A, int B, int C, int... J>
+__device__ __forceinline__ void s_next_range(Regs<1> &n, const Regs<1> &x, const Word<1> &fbs, const Word<1> &g0,
+                                             const Word<1> &g1, std::integer_sequence<int, J...>)
+{
+    ((ex3(LO + J, A, B, C) ? void() : void(n.s[LO + J] = s_next<LO + J, 1>(x, fbs, g0, g1))), ...);
+}
+
+struct S4In {  // next-clock values a wave receives
+    Word<1> a, b, c, d;
+};
+
+// wave 0: in = {r_99, r_67, s_34, s_0} of the current state
+template <int PH>
+__device__ __forceinline__ void s4_clock_rlo(Regs<1> &x, S4In &in, Split4Lds &xl, uint32_t lane)
+{
+    const Word<1> cr = in.c ^ in.b, fbr = in.a;
+    Regs<1> n;
+    n.r[49] = r_next<49, 1>(x, cr, fbr);
+    n.r[33] = r_next<33, 1>(x, cr, fbr);
+    xl.v[PH][kX_R49][lane] = n.r[49].w[0];
+    xl.v[PH][kX_R33][lane] = n.r[33].w[0];
+    lds_barrier();
+    in.a.w[0] = xl.v[PH][kX_R99][lane];
+    in.b.w[0] = xl.v[PH][kX_R67][lane];
+    in.c.w[0] = xl.v[PH][kX_S34][lane];
+    in.d.w[0] = xl.v[PH][kX_S0][lane];
+    __builtin_amdgcn_sched_barrier(0);
+    r_next_range<0, 49, 33, -1>(n, x, cr, fbr, std::make_integer_sequence<int, 50>{});
+#pragma unroll
+    for (int j = 0; j < 50; j++) x.r[j] = n.r[j];
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// wave 1: in = {s_34}; x.r[49] holds the current r_49
+template <int PH>
+__device__ __forceinline__ void s4_clock_rhi(Regs<1> &x, S4In &in, Split4Lds &xl, uint32_t lane)
+{
+    const Word<1> cr = in.a ^ x.r[67], fbr = x.r[99];
+    Regs<1> n;
+    n.r[99] = r_next<99, 1>(x, cr, fbr);
+    n.r[67] = r_next<67, 1>(x, cr, fbr);
+    xl.v[PH][kX_R99][lane] = n.r[99].w[0];
+    xl.v[PH][kX_R67][lane] = n.r[67].w[0];
+    lds_barrier();
+    Word<1> r49;
+    r49.w[0] = xl.v[PH][kX_R49][lane];
+    in.a.w[0] = xl.v[PH][kX_S34][lane];
+    __builtin_amdgcn_sched_barrier(0);
+    r_next_range<50, 99, 67, -1>(n, x, cr, fbr, std::make_integer_sequence<int, 50>{});
+#pragma unroll
+    for (int j = 50; j < 100; j++) x.r[j] = n.r[j];
+    x.r[49] = r49;
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// wave 2: in = {s_99, s_67, r_33}; x.s[50] holds the current s_50
+template <int PH>
+__device__ __forceinline__ void s4_clock_slo(Regs<1> &x, S4In &in, Split4Lds &xl, uint32_t lane)
+{
+    const Word<1> cs = in.b ^ in.c, fbs = in.a;
+    const Word<1> g1 = fbs & cs;
+    const Word<1> g0 = fbs ^ g1;
+    Regs<1> n;
+    n.s[49] = s_next<49, 1>(x, fbs, g0, g1);
+    n.s[34] = s_next<34, 1>(x, fbs, g0, g1);
+    xl.v[PH][kX_S49][lane] = n.s[49].w[0];
+    xl.v[PH][kX_S34][lane] = n.s[34].w[0];
+    xl.v[PH][kX_S0][lane] = fbs.w[0];  // the next s_0
+    lds_barrier();
+    Word<1> s50;
+    s50.w[0] = xl.v[PH][kX_S50][lane];
+    in.a.w[0] = xl.v[PH][kX_S99][lane];
+    in.b.w[0] = xl.v[PH][kX_S67][lane];
+    in.c.w[0] = xl.v[PH][kX_R33][lane];
+    __builtin_amdgcn_sched_barrier(0);
+    s_next_range<0, 49, 34, -1>(n, x, fbs, g0, g1, std::make_integer_sequence<int, 50>{});
+#pragma unroll
+    for (int j = 0; j < 50; j++) x.s[j] = n.s[j];
+    x.s[50] = s50;
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// wave 3: in = {r_33}; x.s[49] holds the current s_49
+template <int PH>
+__device__ __forceinline__ void s4_clock_shi(Regs<1> &x, S4In &in, Split4Lds &xl, uint32_t lane)
+{
+    const Word<1> cs = x.s[67] ^ in.a, fbs = x.s[99];
+    const Word<1> g1 = fbs & cs;
+    const Word<1> g0 = fbs ^ g1;
+    Regs<1> n;
+    n.s[50] = s_next<50, 1>(x, fbs, g0, g1);
+    n.s[99] = s_next<99, 1>(x, fbs, g0, g1);
+    n.s[67] = s_next<67, 1>(x, fbs, g0, g1);
+    xl.v[PH][kX_S50][lane] = n.s[50].w[0];
+    xl.v[PH][kX_S99][lane] = n.s[99].w[0];
+    xl.v[PH][kX_S67][lane] = n.s[67].w[0];
+    lds_barrier();
+    Word<1> s49;
+    s49.w[0] = xl.v[PH][kX_S49][lane];
+    in.a.w[0] = xl.v[PH][kX_R33][lane];
+    __builtin_amdgcn_sched_barrier(0);
+    s_next_range<50, 50, 99, 67>(n, x, fbs, g0, g1, std::make_integer_sequence<int, 50>{});
+#pragma unroll
+    for (int j = 50; j < 100; j++) x.s[j] = n.s[j];
+    x.s[49] = s49;
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// One wave's part of gen_split4_kernel (ROLE = wave index); every role passes 1 + nbits
+// barriers.
+template <int ROLE>
+__device__ __forceinline__ void s4_run(uint32_t *__restrict__ state, size_t pitch, uint32_t voff, uint64_t nbits,
+                                       uint32_t *__restrict__ out, Split4Lds &xl, uint32_t lane)
+{
+    constexpr bool kR = ROLE < 2;
+    constexpr int j0 = ROLE == 0 || ROLE == 2 ? 0 : 50;  // first position of the half
+    constexpr int base = kR ? 0 : 100;                  // r or s planes
+    Regs<1> x;
+    S4In in;
+#pragma unroll
+    for (int j = 0; j < 50; j++) {
+        const Word<1> v = ld_word<1>((const char *)state + (size_t)(base + j0 + j) * pitch + voff);
+        if constexpr (kR) x.r[j0 + j] = v;
+        else x.s[j0 + j] = v;
+    }
+    // publish the state-0 exchange values, then read the others'
+    if constexpr (ROLE == 0) {
+        xl.v[0][kX_R49][lane] = x.r[49].w[0];
+        xl.v[0][kX_R33][lane] = x.r[33].w[0];
+    } else if constexpr (ROLE == 1) {
+        xl.v[0][kX_R99][lane] = x.r[99].w[0];
+        xl.v[0][kX_R67][lane] = x.r[67].w[0];
+    } else if constexpr (ROLE == 2) {
+        xl.v[0][kX_S49][lane] = x.s[49].w[0];
+        xl.v[0][kX_S34][lane] = x.s[34].w[0];
+        xl.v[0][kX_S0][lane] = x.s[0].w[0];
+    } else {
+        xl.v[0][kX_S50][lane] = x.s[50].w[0];
+        xl.v[0][kX_S99][lane] = x.s[99].w[0];
+        xl.v[0][kX_S67][lane] = x.s[67].w[0];
+    }
+    lds_barrier();
+    if constexpr (ROLE == 0) {
+        in.a.w[0] = xl.v[0][kX_R99][lane];
+        in.b.w[0] = xl.v[0][kX_R67][lane];
+        in.c.w[0] = xl.v[0][kX_S34][lane];
+        in.d.w[0] = xl.v[0][kX_S0][lane];
+    } else if constexpr (ROLE == 1) {
+        x.r[49].w[0] = xl.v[0][kX_R49][lane];
+        in.a.w[0] = xl.v[0][kX_S34][lane];
+    } else if constexpr (ROLE == 2) {
+        x.s[50].w[0] = xl.v[0][kX_S50][lane];
+        in.a.w[0] = xl.v[0][kX_S99][lane];
+        in.b.w[0] = xl.v[0][kX_S67][lane];
+        in.c.w[0] = xl.v[0][kX_R33][lane];
+    } else {
+        x.s[49].w[0] = xl.v[0][kX_S49][lane];
+        in.a.w[0] = xl.v[0][kX_R33][lane];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    auto clock = [&](auto ph) {
+        constexpr int PH = decltype(ph)::value;
+        if constexpr (ROLE == 0) s4_clock_rlo<PH>(x, in, xl, lane);
+        else if constexpr (ROLE == 1) s4_clock_rhi<PH>(x, in, xl, lane);
+        else if constexpr (ROLE == 2) s4_clock_slo<PH>(x, in, xl, lane);
+        else s4_clock_shi<PH>(x, in, xl, lane);
+    };
+    // clock t writes buffer (t + 1) & 1: two clocks per iteration keep the buffer index (and
+    // the register sets of the functional update) fixed; an odd last clock writes buffer 1
+    char *plane = (char *)out;  // wave-uniform (used by wave 0)
+    const uint64_t npairs = nbits / 2;
+    for (uint64_t i = 0; i < npairs; i++) {
+        if constexpr (ROLE == 0) {
+            store_plane<1>(plane, voff, x.r[0] ^ in.d);
+            plane += pitch;
+        }
+        clock(std::integral_constant<int, 1>{});
+        if constexpr (ROLE == 0) {
+            store_plane<1>(plane, voff, x.r[0] ^ in.d);
+            plane += pitch;
+        }
+        clock(std::integral_constant<int, 0>{});
+    }
+    if (nbits & 1) {
+        if constexpr (ROLE == 0) store_plane<1>(plane, voff, x.r[0] ^ in.d);
+        clock(std::integral_constant<int, 1>{});
+    }
+    uint32_t v = voff;
+    asm volatile("" : "+v"(v));  // keep the load addresses from living across the loop
+#pragma unroll
+    for (int j = 0; j < 50; j++) {
+        if constexpr (kR) st_word<1>((char *)state + (size_t)(base + j0 + j) * pitch + v, x.r[j0 + j]);
+        else st_word<1>((char *)state + (size_t)(base + j0 + j) * pitch + v, x.s[j0 + j]);
+    }
+}
+
+// Bit-plane output only (the row-major layouts reach it through the staged transpose).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kSplit4Waves, kSplit4Waves))) void
+gen_split4_kernel(uint32_t *__restrict__ state, uint32_t nslices, uint64_t nbits, uint32_t *__restrict__ out)
+{
+    __shared__ Split4Lds xl;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t g = blockIdx.x * 64u + lane;
+    // lanes past the last slice run a copy of the block's first slice (see gen_split_kernel)
+    const uint32_t gs = g < nslices ? g : blockIdx.x * 64u;
+    const size_t pitch = (size_t)nslices * 4u;
+    const uint32_t voff = gs * 4u;
+    if (wave == 0) s4_run<0>(state, pitch, voff, nbits, out, xl, lane);
+    else if (wave == 1) s4_run<1>(state, pitch, voff, nbits, out, xl, lane);
+    else if (wave == 2) s4_run<2>(state, pitch, voff, nbits, out, xl, lane);
+    else s4_run<3>(state, pitch, voff, nbits, out, xl, lane);
 }
 
 // a5, staged: a chunk of bit-planes (as the generate kernels write them) turned into
@@ -464,17 +704,28 @@ mickey_state *init_impl(const uint8_t *keys, const uint8_t *ivs, const uint8_t *
     return st;
 }
 
-// The split schedule doubles the waves of a call.  Measured on MI355X (1024 SIMDs), it
-// is faster up to one one-wave-schedule wave per SIMD (1.5x at 256 waves, 1.25x at
-// 1024 in the bit-plane layout) and slower from 1536 waves on, where its per-clock
-// exchange costs more than the extra waves gain.
-bool use_split(const mickey_state *st)
+// Which kernel generates: the split schedules multiply the waves of a call by 2 or 4 at the
+// cost of a per-clock exchange.  Measured on MI355X (1024 SIMDs, bit-planes, 4096 clocks),
+// against the one-wave kernel: four-wave split 2.3x at 2^18 instances, 2.0x at 2^20, 1.2x
+// at 2^21 (the two-wave split is equal there), 1.07x at 3*2^20, 0.94x at 2^22 where the
+// one-wave kernel fills every SIMD with two waves.  The automatic schedule takes the
+// four-wave split below that point.
+enum class Gen { OneWave, Split2, Split4 };
+
+Gen pick_gen(const mickey_state *st)
 {
-    if (st->schedule == MICKEY_SCHED_SPLIT) return true;
-    if (st->schedule == MICKEY_SCHED_ONE_WAVE || st->word_bits != 32) return false;
+    if (st->word_bits != 32 || st->schedule == MICKEY_SCHED_ONE_WAVE) return Gen::OneWave;
+    if (st->schedule == MICKEY_SCHED_SPLIT) return Gen::Split2;
+    if (st->schedule == MICKEY_SCHED_SPLIT4) return Gen::Split4;
     const size_t waves = (st->nslices + 63) / 64;
-    return waves <= (size_t)st->simds;
+    return waves < 2 * (size_t)st->simds ? Gen::Split4 : Gen::OneWave;
 }
+
+bool use_split4(const mickey_state *st) { return pick_gen(st) == Gen::Split4; }
+
+// The fused row-major path has one-wave and two-wave kernels; the four-wave schedule
+// uses the two-wave one there.
+bool use_split(const mickey_state *st) { return pick_gen(st) != Gen::OneWave; }
 
 // Staged row-major delivery: clocks per chunk for chunk buffers of at most 512 MiB each, in
 // whole transpose tiles (1024 clocks) and at most 8192; 0 when even one tile of planes
@@ -558,7 +809,10 @@ int launch_generate_planes(mickey_state *st, uint64_t nbits, uint32_t *out)
 {
     const size_t pitch = st->nslices * 4;
     const unsigned nblocks = (unsigned)((st->nslices + 63) / 64);
-    if (use_split(st)) {
+    if (use_split4(st)) {
+        hipLaunchKernelGGL(gen_split4_kernel, dim3(nblocks), dim3(256), 0, st->stream, st->planes,
+                           (uint32_t)st->nslices, nbits, out);
+    } else if (use_split(st)) {
         hipLaunchKernelGGL(gen_split_kernel<false>, dim3(nblocks), dim3(128), 0, st->stream, st->planes,
                            (uint32_t)st->nslices, (uint32_t)st->n, nbits, out, nullptr, nullptr);
     } else if (st->word_bits == 32) {
@@ -666,7 +920,7 @@ int mickey_set_word_bits(mickey_state *st, int word_bits)
     if (!st) return fail(MICKEY_EINVAL, "mickey_set_word_bits: NULL state");
     if (word_bits != 32 && word_bits != 64)
         return fail(MICKEY_ENOSYS, "mickey_set_word_bits: %d-bit words are not supported", word_bits);
-    if (word_bits == 64 && st->schedule == MICKEY_SCHED_SPLIT)
+    if (word_bits == 64 && (st->schedule == MICKEY_SCHED_SPLIT || st->schedule == MICKEY_SCHED_SPLIT4))
         return fail(MICKEY_EINVAL, "mickey_set_word_bits: the split schedule uses 32-bit words");
     st->word_bits = word_bits;
     return ok();
@@ -684,9 +938,10 @@ int mickey_set_transpose(mickey_state *st, int mode)
 int mickey_set_schedule(mickey_state *st, int schedule)
 {
     if (!st) return fail(MICKEY_EINVAL, "mickey_set_schedule: NULL state");
-    if (schedule != MICKEY_SCHED_AUTO && schedule != MICKEY_SCHED_ONE_WAVE && schedule != MICKEY_SCHED_SPLIT)
+    if (schedule != MICKEY_SCHED_AUTO && schedule != MICKEY_SCHED_ONE_WAVE && schedule != MICKEY_SCHED_SPLIT &&
+        schedule != MICKEY_SCHED_SPLIT4)
         return fail(MICKEY_EINVAL, "mickey_set_schedule: unknown schedule %d", schedule);
-    if (schedule == MICKEY_SCHED_SPLIT && st->word_bits != 32)
+    if ((schedule == MICKEY_SCHED_SPLIT || schedule == MICKEY_SCHED_SPLIT4) && st->word_bits != 32)
         return fail(MICKEY_EINVAL, "mickey_set_schedule: the split schedule uses 32-bit words");
     st->schedule = schedule;
     return ok();

@@ -11,7 +11,7 @@ from .build import LIB_PATH
 
 OK, EINVAL, ENOMEM, EDEVICE, ERANGE, ENOSYS = 0, -1, -2, -3, -4, -5
 BITSLICED, ROWMAJOR_U32, ROWMAJOR_F32 = 0, 1, 2
-SCHED_AUTO, SCHED_ONE_WAVE, SCHED_SPLIT = 0, 1, 2
+SCHED_AUTO, SCHED_ONE_WAVE, SCHED_SPLIT, SCHED_SPLIT4 = 0, 1, 2, 3
 TRANSPOSE_AUTO, TRANSPOSE_FUSED, TRANSPOSE_STAGED = 0, 1, 2
 MAX_BITS_PER_IV = 1 << 40
 PACKED_STATE_BYTES = 25
@@ -275,7 +275,7 @@ class Mickey:
         _check(load_library().mickey_set_word_bits(self._h, int(bits)))
 
     def set_schedule(self, schedule: int) -> None:
-        """SCHED_AUTO, SCHED_ONE_WAVE or SCHED_SPLIT (mickey_set_schedule)."""
+        """SCHED_AUTO, SCHED_ONE_WAVE, SCHED_SPLIT or SCHED_SPLIT4 (mickey_set_schedule)."""
         _check(load_library().mickey_set_schedule(self._h, int(schedule)))
 
     def set_transpose(self, mode: int) -> None:

@@ -24,7 +24,7 @@ def make(keys, ivs, ivb=None):
     return mickey.Mickey(to_dev(keys), to_dev(ivs), None if ivb is None else to_dev(ivb))
 
 
-SCHEDULES = [mickey.SCHED_ONE_WAVE, mickey.SCHED_SPLIT]
+SCHEDULES = [mickey.SCHED_ONE_WAVE, mickey.SCHED_SPLIT, mickey.SCHED_SPLIT4]
 
 
 def gpu_bitsliced(keys, ivs, ivb, nbits, word_bits=32, schedule=mickey.SCHED_AUTO):
@@ -232,7 +232,7 @@ def test_error_paths():
         m.set_word_bits(16)
     assert e.value.code == mickey.ENOSYS
     with pytest.raises(mickey.MickeyError) as e:
-        m.set_schedule(3)
+        m.set_schedule(4)
     assert e.value.code == mickey.EINVAL
     with pytest.raises(mickey.MickeyError) as e:
         m.set_transpose(3)
@@ -267,7 +267,7 @@ def sample_indices(n, k, seed):
 def test_plain_4m_sampled_parity():
     """2^22 instances, 8192 bits, bitsliced, the launch configuration the benchmark times:
     all lanes of the first and last slice plus seeded random instances against the oracle;
-    word widths 32 and 64 and the split schedule must give identical bytes."""
+    word widths 32 and 64 and the split schedules must give identical bytes."""
     seed, n, nbits, _ = synth.workload("plain-4m")
     keys, ivs = synth.keys_ivs(seed, n)
     m = make(keys, ivs)
@@ -283,12 +283,14 @@ def test_plain_4m_sampled_parity():
     out2 = m2.generate(nbits)
     assert torch.equal(out, out2)
     m2.close()
-    m3 = make(keys, ivs)
-    m3.set_schedule(mickey.SCHED_SPLIT)
-    out3 = m3.generate(nbits)
-    assert torch.equal(out, out3)
+    for sched in (mickey.SCHED_SPLIT, mickey.SCHED_SPLIT4):
+        m3 = make(keys, ivs)
+        m3.set_schedule(sched)
+        out3 = m3.generate(nbits)
+        assert torch.equal(out, out3), sched
+        m3.close()
+        del out3
     m.close()
-    m3.close()
 
 
 def test_rowmajor_1m_sampled_parity():
@@ -317,7 +319,7 @@ def test_rowmajor_1m_sampled_parity():
 
 @pytest.mark.parametrize("n", [64 * 33, 64 * 1024 + 96])
 def test_schedules_agree_across_launch_shapes(n):
-    """Both schedules, every instance, a few hundred clocks: one call per layout and
+    """Every schedule, every instance, a few hundred clocks: one call per layout and
     a clock count that ends off the unrolled loop, at block counts that leave a
     partial last workgroup (lanes past the last slice)."""
     keys, ivs, ivb = random_inputs(n, n)
@@ -330,8 +332,9 @@ def test_schedules_agree_across_launch_shapes(n):
         exp, bits = m.export_state()
         outs.append((a, b, exp, bits))
         m.close()
-    (a0, b0, e0, n0), (a1, b1, e1, n1) = outs
-    assert torch.equal(a0, a1) and torch.equal(b0, b1) and torch.equal(e0, e1) and n0 == n1 == 299
+    a0, b0, e0, n0 = outs[0]
+    for a1, b1, e1, n1 in outs[1:]:
+        assert torch.equal(a0, a1) and torch.equal(b0, b1) and torch.equal(e0, e1) and n0 == n1 == 299
     idx = sample_indices(n, 96, 9)
     want = oracle_bits(keys[idx], ivs[idx], ivb[idx], 299)
     ti = torch.from_numpy(idx).to(DEV)
