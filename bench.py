@@ -273,7 +273,8 @@ def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 
                                   "batch_speedup": round(serial_ms / batch_ms, 1)}}
 
 
-def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: float, rate: float = 20000.0,
+def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: float, lat_ratio: int = 8,
+                lat_streams: int = 16384, lat_threshold: int = 1 << 20, rate: float = 20000.0,
                 nstates: int = 10 ** 6, budget: int = 64 << 30, chunk: int = 64 << 10, sat_seconds: float = 3.0,
                 nverify: int = 16):
     """Served generation over 10^6 resident states (splitmix64 seed 5 keys and 80-bit
@@ -301,6 +302,10 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
     nslices, qclocks = 32768, 2048
     srv = mickey.Server(init, nslices=nslices, quantum_clocks=qclocks, budget_bytes=budget)
     srv.set_chunk(chunk)
+    # size-aware routing: what is left of a request of lat_threshold bits or more takes one
+    # of lat_streams latency streams (one request per four lanes), lat_ratio x the quantum
+    # per step
+    srv.set_latency(lat_streams, threshold_bits=lat_threshold, clocks_per_quantum=lat_ratio * qclocks)
     lat = np.full(n, np.inf)
     run_s = np.zeros(n)  # admission to completion
     t0 = time.monotonic_ns()
@@ -375,8 +380,10 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
     out["open_loop"] = {
         "workload": "10^6 resident states; Poisson arrivals %.0f/s for %.1f s; state uniform; size log-uniform "
                     "4 KiB..%d KiB; row-major u32 output delivered in %d KiB chunks; 64 GiB output budget; "
-                    "%d slots x 32 lanes; quantum %d clocks; stopped %.0f s after the last arrival" % (
-                        rate, duration, max_bytes >> 10, chunk >> 10, nslices, qclocks, drain),
+                    "%d slots x 32 lanes; quantum %d clocks; requests with >= %d KiB left routed to %d "
+                    "latency streams (%d clocks per quantum) while the bit lanes are at most half busy; stopped "
+                    "%.0f s after the last arrival" % (rate, duration, max_bytes >> 10, chunk >> 10, nslices, qclocks,
+                                                       lat_threshold >> 13, lat_streams, lat_ratio * qclocks, drain),
         "requests": n, "completed": int(done.sum()), "completed_fraction": round(float(done.mean()), 4),
         "bits_offered": int(nbits.sum()), "bits_delivered": st["bits_delivered"], "span_s": round(span, 3),
         "served_gbit_s": round(st["bits_delivered"] / span / 1e9, 3),
@@ -384,6 +391,9 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
         "latency_s": {"p50": p50, "p99": p99, "p50_lower_bound": p50_lb, "p99_lower_bound": p99_lb,
                       "max_completed": round(float(lat[done].max()), 4) if done.any() else None},
         "stream_rate_mbit_s_per_request": rate_mbit,
+        "host_s": {"blocked_on_gpu": round(st["host_wait_ns"] * 1e-9, 3),
+                   "retiring": round(st["host_retire_ns"] * 1e-9, 3),
+                   "admitting": round(st["host_admit_ns"] * 1e-9, 3)},
         "chunks": nchunks, "peak_running": peak_running, "steps": st["steps"],
         "mean_quantum_ms": round(st["quantum_ns"] / max(st["steps"], 1) / 1e6, 3),
         "same_as_plain_kernel_sample": {"requests": checked, "mismatches": mism,
@@ -479,8 +489,13 @@ def main() -> int:
     ap.add_argument("--no-aes", action="store_true", help="skip the bitsliced AES-CTR leg")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="Poisson arrival window of the served run")
     ap.add_argument("--serve-max-kib", type=int, default=64 << 10, help="largest served request (KiB)")
-    ap.add_argument("--serve-drain", type=float, default=30.0,
+    ap.add_argument("--serve-drain", type=float, default=90.0,
                     help="seconds the open-loop served run continues after the last arrival")
+    ap.add_argument("--serve-lat-ratio", type=int, default=8,
+                    help="open loop: latency-stream clocks per quantum, as a multiple of the quantum")
+    ap.add_argument("--serve-lat-streams", type=int, default=16384, help="open loop: latency streams (0: off)")
+    ap.add_argument("--serve-lat-kib", type=int, default=128,
+                    help="open loop: requests with at least this many KiB left take latency streams")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--code-hash", action="store_true", help="print the headline kernel's code hash and exit")
@@ -627,7 +642,8 @@ def main() -> int:
         res["batch_10k"] = bench_batch(torch, mickey, synth)
     if not args.no_serve:
         res["serve"] = bench_serve(torch, mickey, synth, args.serve_seconds, args.serve_max_kib << 10,
-                                   args.serve_drain)
+                                   args.serve_drain, args.serve_lat_ratio, args.serve_lat_streams,
+                                   args.serve_lat_kib << 13)
     print(json.dumps(res), flush=True)
     return 0
 

@@ -324,6 +324,20 @@ int mickey_server_set_chunk(mickey_server *s, uint64_t chunk_bytes);
  *              mickey_set_schedule (AUTO: split up to one one-wave wave per SIMD).
  * MICKEY_EINVAL for FUSED with SPLIT, or STAGED / SPLIT without the buffer. */
 int mickey_server_set_kernel(mickey_server *s, int schedule, int transpose);
+
+/* Latency streams (the paper's Sec. VI: delay is the GPU's drawback): the part of a
+ * request that still has at least threshold_bits to go is admitted, when one is free, to
+ * one of `streams` (at most 16384) latency streams instead of a bit lane, while at most
+ * half of the bit lanes are busy.  A latency stream is four lanes of one wave holding the
+ * request's registers as words; it advances clocks_per_quantum clocks per quantum (a
+ * positive multiple of 32), beside the bitsliced quantum on a second stream, at ~27 VALU
+ * per clock instead of ~330 per 32 requests: several times faster per request, ~10x the
+ * device work per bit.  Output bytes are the same either way.  Defaults at creation:
+ * 16384 streams, 2^20 bits, 8 x the quantum.  streams = 0
+ * turns routing off.  MICKEY_EINVAL while latency streams or quanta are in flight (call
+ * it between mickey_server_wait and new work). */
+int mickey_server_set_latency(mickey_server *s, uint32_t streams, uint64_t threshold_bits,
+                              uint64_t clocks_per_quantum);
 int64_t mickey_server_poll_chunks(mickey_server *s, mickey_chunk *out, size_t cap);
 int mickey_server_release_chunks(mickey_server *s, const uint64_t *handles, size_t n);
 /* Copy the first nwords words of a delivered, not yet released chunk into dst (device);

@@ -27,6 +27,7 @@
 #include "arena.h"
 #include "mickey_device.h"
 #include "mickey_host.h"
+#include "mickey_wordpar.h"
 
 #include <hip/hip_runtime.h>
 
@@ -59,14 +60,24 @@ struct Admit {
 
 // Admission metadata: lane `lane` takes resident state `sid` with an output of `words`
 // words at `out`, and is flagged fresh in its slice's mask (one atomic per admission); the
-// next quantum gathers the fresh lanes' states into its registers.
-__global__ __launch_bounds__(256) void admit_kernel(const Admit *__restrict__ adm, uint32_t nadm,
+// next quantum gathers the fresh lanes' states into its registers.  Lane ids from nlanes
+// on are latency streams (lane - nlanes), flagged fresh in their own word.
+__global__ __launch_bounds__(256) void admit_kernel(const Admit *__restrict__ adm, uint32_t nadm, uint32_t nlanes,
                                                     uint32_t **lane_out, uint32_t *lane_left, uint32_t *lane_sid,
-                                                    uint32_t *fresh)
+                                                    uint32_t *fresh, uint32_t **lat_out, uint32_t *lat_left,
+                                                    uint32_t *lat_sid, uint32_t *lat_fresh)
 {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nadm) return;
     const Admit a = adm[k];
+    if (a.lane >= nlanes) {
+        const uint32_t j = a.lane - nlanes;
+        lat_out[j] = a.out;
+        lat_left[j] = a.words;
+        lat_sid[j] = a.sid;
+        lat_fresh[j] = 1u;
+        return;
+    }
     lane_out[a.lane] = a.out;
     lane_left[a.lane] = a.words;
     lane_sid[a.lane] = a.sid;
@@ -254,6 +265,164 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     }
 }
 
+// ---------------------------------------------------------------------------------
+// Latency streams (the paper's Sec. VI names delay as the drawback of GPU generators): a
+// request routed here advances one clock per ~27 VALU operations of one wave instead of
+// one per bitsliced clock (~330 operations for 32 requests); with one wave issuing at
+// most ~0.4 instructions/ns, that is ~70 ns per clock for the request against several
+// hundred for a bit lane of a partly filled launch.  One request per quad of lanes: lane
+// q keeps word q of R and of S in the word-parallel layout of mickey_wordpar.h (bit i of
+// a register is bit i % 32 of word i / 32).  Per clock the quad XOR-reduces each lane's
+// share of the four bits that steer the clock (s_34 ^ r_67 = c_R, r_33 ^ s_67 = c_S,
+// r_99 = fb_R, s_99 = fb_S) with two DPP swaps, fetches its neighbours' words for the
+// shifts with DPP quad permutes, and updates its two words as the word-parallel clock
+// does.  (The one-lane word-parallel clock is ~52 operations: half the speed per request.)
+
+constexpr uint32_t kLatStreams = 16384;  // latency stream capacity of a server
+
+constexpr int qp(int a, int b, int c, int d) { return a | (b << 2) | (c << 4) | (d << 6); }
+template <int CTRL>
+__device__ __forceinline__ uint32_t qperm(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t bitmask_i(uint32_t v, int b) { return (uint32_t)((int32_t)(v << (31 - b)) >> 31); }
+
+struct QuadMasks {
+    uint32_t taps, comp0, comp1, fb0, fb1, inner;  // word q of the position masks
+    uint32_t prev;                                 // 0 in lane 0: nothing shifts into r_0, s_0
+    uint32_t ra, rm, sa, sm;                       // this lane's share of the steering bits
+};
+
+__device__ __forceinline__ uint32_t pick4(uint32_t q, uint32_t a, uint32_t b, uint32_t c, uint32_t d)
+{
+    return q == 0 ? a : q == 1 ? b : q == 2 ? c : d;
+}
+
+__device__ __forceinline__ QuadMasks quad_masks(uint32_t q)
+{
+    QuadMasks m;
+    m.taps = pick4(q, kWM.taps[0], kWM.taps[1], kWM.taps[2], kWM.taps[3]);
+    m.comp0 = pick4(q, kWM.comp0[0], kWM.comp0[1], kWM.comp0[2], kWM.comp0[3]);
+    m.comp1 = pick4(q, kWM.comp1[0], kWM.comp1[1], kWM.comp1[2], kWM.comp1[3]);
+    m.fb0 = pick4(q, kWM.fb0[0], kWM.fb0[1], kWM.fb0[2], kWM.fb0[3]);
+    m.fb1 = pick4(q, kWM.fb1[0], kWM.fb1[1], kWM.fb1[2], kWM.fb1[3]);
+    m.inner = pick4(q, kWM.inner[0], kWM.inner[1], kWM.inner[2], kWM.inner[3]);
+    m.prev = q ? 0xFFFFFFFFu : 0u;
+    // v bit 0: c_R (s_34 in lane 1, r_67 in lane 2), bit 1: c_S (r_33 in lane 1, s_67 in
+    // lane 2), bit 2: fb_R (r_99, lane 3), bit 3: fb_S (s_99, lane 3)
+    m.ra = pick4(q, 0, 0, 3, 1);
+    m.rm = pick4(q, 0, 2, 1, 4);
+    m.sa = pick4(q, 0, 2, 2, 0);
+    m.sm = pick4(q, 0, 1, 2, 8);
+    return m;
+}
+
+__device__ __forceinline__ void quad_clock(uint32_t &r, uint32_t &s, const QuadMasks &m)
+{
+    uint32_t v = ((r >> m.ra) & m.rm) ^ ((s >> m.sa) & m.sm);
+    v ^= qperm<qp(1, 0, 3, 2)>(v);
+    v ^= qperm<qp(2, 3, 0, 1)>(v);
+    const uint32_t cr = bitmask_i(v, 0), cs = bitmask_i(v, 1), fbr = bitmask_i(v, 2), fbs = bitmask_i(v, 3);
+    const uint32_t rp = qperm<qp(0, 0, 1, 2)>(r) & m.prev;
+    const uint32_t sp = qperm<qp(0, 0, 1, 2)>(s) & m.prev;
+    const uint32_t sn = qperm<qp(1, 2, 3, 3)>(s);
+    const uint32_t rl = __builtin_amdgcn_alignbit(r, rp, 31);  // register shifted up by one
+    const uint32_t sl = __builtin_amdgcn_alignbit(s, sp, 31);
+    const uint32_t sr = __builtin_amdgcn_alignbit(sn, s, 1);   // shifted down by one
+    const uint32_t t = __builtin_amdgcn_bitop3_b32(rl, fbr, m.taps, TA ^ (TB & TC));
+    r = __builtin_amdgcn_bitop3_b32(t, cr, r, TA ^ (TB & TC));
+    const uint32_t qv = __builtin_amdgcn_bitop3_b32(s, m.comp0, m.inner, (TA ^ TB) & TC);
+    const uint32_t y = sr ^ m.comp1;
+    const uint32_t h = __builtin_amdgcn_bitop3_b32(sl, qv, y, TA ^ (TB & TC));
+    const uint32_t fsel = __builtin_amdgcn_bitop3_b32(cs, m.fb1, m.fb0, (TA & TB) | (~TA & TC));
+    s = __builtin_amdgcn_bitop3_b32(h, fbs, fsel, TA ^ (TB & TC));
+}
+
+// Word q of R and S from the packed state (25 bytes, r_0..r_99 s_0..s_99, MSB first).
+__device__ __forceinline__ void quad_gather(const uint8_t *src, uint32_t q, uint32_t &r, uint32_t &s)
+{
+    r = 0u;
+    s = 0u;
+    for (uint32_t b = 0; b < 32u; b++) {
+        const uint32_t i = 32u * q + b;
+        if (i >= 100u) break;
+        const uint32_t js = 100u + i;
+        r |= ((uint32_t)(src[i >> 3] >> (7u - (i & 7u))) & 1u) << b;
+        s |= ((uint32_t)(src[js >> 3] >> (7u - (js & 7u))) & 1u) << b;
+    }
+}
+
+// Lane 0 of the quad packs the quad's words into 25 bytes at dst (all four lanes call it).
+__device__ __forceinline__ void quad_write_back(uint32_t r, uint32_t s, uint32_t q, uint8_t *dst)
+{
+    const uint32_t rw[4] = {qperm<qp(0, 0, 0, 0)>(r), qperm<qp(1, 1, 1, 1)>(r), qperm<qp(2, 2, 2, 2)>(r),
+                            qperm<qp(3, 3, 3, 3)>(r)};
+    const uint32_t sw[4] = {qperm<qp(0, 0, 0, 0)>(s), qperm<qp(1, 1, 1, 1)>(s), qperm<qp(2, 2, 2, 2)>(s),
+                            qperm<qp(3, 3, 3, 3)>(s)};
+    if (q) return;
+#pragma unroll
+    for (int byte = 0; byte < 25; byte++) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int j = 8 * byte + k;
+            const uint32_t bit = j < 100 ? (rw[j >> 5] >> (j & 31)) & 1u : (sw[(j - 100) >> 5] >> ((j - 100) & 31)) & 1u;
+            v |= bit << (7 - k);
+        }
+        dst[byte] = (uint8_t)v;
+    }
+}
+
+// One quantum of the latency streams: every busy stream runs up to nwords x 32 clocks,
+// storing one output word per 32 clocks (lane 0), then keeps its words in lat_state; a
+// stream whose words end packs its state back into the pool and joins the completion
+// list as id_base + stream.  Streams are whole quads, so every DPP stays inside a quad
+// whose lanes are all active.
+__global__ __launch_bounds__(64) void latency_quantum_kernel(uint32_t *__restrict__ lat_state, uint32_t nstreams,
+                                                             uint32_t nwords, uint32_t **lat_out,
+                                                             uint32_t *__restrict__ lat_left,
+                                                             const uint32_t *__restrict__ lat_sid,
+                                                             uint32_t *__restrict__ lat_fresh, uint8_t *__restrict__ pool,
+                                                             uint32_t id_base, uint32_t *__restrict__ done_list,
+                                                             uint32_t *__restrict__ done_count)
+{
+    const uint32_t t = blockIdx.x * 64u + threadIdx.x, k = t >> 2, q = t & 3u;
+    if (k >= nstreams) return;
+    const uint32_t left = lat_left[k];
+    if (!left) return;
+    uint32_t r, s;
+    if (lat_fresh[k]) {
+        quad_gather(pool + 25ull * lat_sid[k], q, r, s);
+    } else {
+        r = lat_state[8u * k + 2u * q];
+        s = lat_state[8u * k + 2u * q + 1u];
+    }
+    const QuadMasks m = quad_masks(q);
+    uint32_t *out = lat_out[k];
+    const uint32_t nw = left < nwords ? left : nwords;
+    for (uint32_t w = 0; w < nw; w++) {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int b = 0; b < 32; b++) {
+            acc = __builtin_amdgcn_alignbit(r ^ s, acc, 1);  // z = r_0 ^ s_0 (lane 0) enters at bit 31
+            quad_clock(r, s, m);
+        }
+        if (q == 0) store_global(out + w, __builtin_bitreverse32(acc));  // first bit in the MSB
+    }
+    if (nw == left) {
+        quad_write_back(r, s, q, pool + 25ull * lat_sid[k]);
+        if (q == 0) done_list[atomicAdd(done_count, 1u)] = id_base + k;
+    }
+    if (q == 0) {
+        lat_left[k] = left - nw;
+        lat_out[k] = out + nw;
+        lat_fresh[k] = 0u;
+    }
+    lat_state[8u * k + 2u * q] = r;
+    lat_state[8u * k + 2u * q + 1u] = s;
+}
+
 struct Request {
     uint64_t id;
     uint32_t sid;
@@ -313,6 +482,17 @@ struct mickey_server {
     uint32_t sub_blocks = 0;  // blocks per staged launch (0: staging not available)
     int schedule = MICKEY_SCHED_AUTO, transpose = MICKEY_TRANSPOSE_AUTO;
     int simds = 1024;
+    // latency streams: lane ids nlanes .. nlanes + kLatStreams - 1
+    uint32_t *lat_state = nullptr;  // [kLatStreams][4 lanes][r, s]
+    uint32_t **lat_out = nullptr;
+    uint32_t *lat_left = nullptr, *lat_sid = nullptr, *lat_fresh = nullptr;
+    uint32_t lat_streams = 0;          // streams in use (0: routing off)
+    uint64_t lat_threshold_words = 0;  // requests with at least this many words left go there
+    uint32_t lat_words = 0;            // output words per stream per quantum
+    std::vector<uint32_t> lat_free;    // free stream indices
+    uint32_t lat_busy = 0;
+    hipStream_t side = nullptr;  // latency streams run here, beside the bitsliced quantum
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     uint32_t *done_list = nullptr, *done_count = nullptr;
     Admit *dadm = nullptr;
     uint32_t *arena = nullptr;
@@ -358,7 +538,9 @@ void destroy(mickey_server *s)
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (void *p : {(void *)s->pool, (void *)s->planes, (void *)s->lane_out, (void *)s->lane_left,
                     (void *)s->lane_sid, (void *)s->fresh, (void *)s->sink, (void *)s->done_list, (void *)s->dadm,
-                    (void *)s->arena, (void *)s->zplanes, (void *)s->row_dst, (void *)s->row_cnt})
+                    (void *)s->arena, (void *)s->zplanes, (void *)s->row_dst, (void *)s->row_cnt,
+                    (void *)s->lat_state, (void *)s->lat_out, (void *)s->lat_left, (void *)s->lat_sid,
+                    (void *)s->lat_fresh})
         if (p) (void)hipFree(p);
     if (s->hadm) (void)hipHostFree(s->hadm);
     if (s->hcount) (void)hipHostFree(s->hcount);
@@ -366,6 +548,12 @@ void destroy(mickey_server *s)
     for (hipEvent_t e : s->ev)
         if (e) (void)hipEventDestroy(e);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->side) {
+        (void)hipStreamSynchronize(s->side);
+        (void)hipStreamDestroy(s->side);
+    }
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
     delete s;
 }
 
@@ -621,6 +809,23 @@ void pass_state(mickey_server *s, uint32_t sid)
     s->ready_q.push(nx);
 }
 
+// Size-aware routing: up to `streams` latency streams, for requests with at least
+// threshold_bits left; each stream runs clocks_per_quantum clocks per quantum.
+void set_latency(mickey_server *s, uint32_t streams, uint64_t threshold_bits, uint64_t clocks_per_quantum)
+{
+    s->lat_streams = streams;
+    s->lat_threshold_words = (threshold_bits + 31) / 32;
+    s->lat_words = (uint32_t)(clocks_per_quantum / 32);
+    s->lat_free.clear();
+    for (uint32_t k = streams; k-- > 0;) s->lat_free.push_back(k);  // lowest index first
+}
+
+// Chunk-block cache of a lane: its slice's, or one shared by the latency streams.
+uint32_t cache_index(const mickey_server *s, uint32_t lane)
+{
+    return lane < s->nlanes ? lane / 32u : (uint32_t)s->nslices;
+}
+
 // Wait for the oldest in-flight quantum and retire the requests it completed.
 int retire_oldest(mickey_server *s)
 {
@@ -634,12 +839,17 @@ int retire_oldest(mickey_server *s)
     s->ns_wait += t1 - tw;
     s->quanta_ns += t1 - s->launch_ns[b];
     const uint32_t ndone = s->hcount[b];
-    const uint32_t *list = s->hlist + (size_t)b * s->nlanes;
+    const uint32_t *list = s->hlist + (size_t)b * (s->nlanes + kLatStreams);
     for (uint32_t k = 0; k < ndone; k++) {
         const uint32_t lane = list[k];
         Request &r = s->reqs[s->lane_req[lane]];
         s->lane_req[lane] = ~0ull;
-        s->free_lanes.push_back(lane);
+        if (lane < s->nlanes) {
+            s->free_lanes.push_back(lane);
+        } else {
+            s->lat_free.push_back(lane - (uint32_t)s->nlanes);
+            s->lat_busy--;
+        }
         r.lane = kNoRequest;
         r.words_done += r.cur_words;
         s->state_bits[r.sid] += 32ull * r.cur_words;
@@ -655,7 +865,7 @@ int retire_oldest(mickey_server *s)
                 h = s->slots.size();
                 s->slots.emplace_back();
             }
-            s->slots[h] = ChunkSlot{r.out_off, r.out_granted, r.cur_words, lane / 32u, true};
+            s->slots[h] = ChunkSlot{r.out_off, r.out_granted, r.cur_words, cache_index(s, lane), true};
             s->ready.push_back(mickey_chunk{r.id, h, r.words_done - r.cur_words, r.cur_words, s->arena + r.out_off,
                                             last ? 1ull : 0ull});
         }
@@ -682,10 +892,15 @@ bool admit_next(mickey_server *s, Request &r, uint64_t t_admit)
     const uint32_t words = r.chunk_words ? (uint32_t)std::min<uint64_t>(left, r.chunk_words) : (uint32_t)left;
     // a chunk always reserves a whole chunk, so that chunk blocks share one size class
     const size_t reserve = r.chunk_words ? r.chunk_words : words;
-    if (s->free_lanes.empty()) return false;
-    const uint32_t lane = s->free_lanes.back();
+    // size-aware routing: what is left of a long request takes a latency stream if one is free
+    // (only while the bit lanes are at most half busy: a latency stream costs ~5x the
+    // device work per bit, which a full launch of bit lanes cannot spare)
+    const bool lat = s->lat_streams && left >= s->lat_threshold_words && !s->lat_free.empty() &&
+                     2 * s->free_lanes.size() >= s->nlanes;
+    if (!lat && s->free_lanes.empty()) return false;
+    const uint32_t lane = lat ? (uint32_t)s->nlanes + s->lat_free.back() : s->free_lanes.back();
     size_t off = 0, granted = 0;
-    auto &cache = s->slice_blocks[lane / 32u];
+    auto &cache = s->slice_blocks[cache_index(s, lane)];
     const size_t cls_words = serve_arena::Arena::class_words(serve_arena::Arena::cls(reserve));
     if (r.chunk_words && !cache.empty() && cache.back().second == cls_words) {
         off = cache.back().first;
@@ -701,7 +916,12 @@ bool admit_next(mickey_server *s, Request &r, uint64_t t_admit)
         s->slice_cached = 0;
         if (!s->alloc.alloc(reserve, &off, &granted)) return false;
     }
-    s->free_lanes.pop_back();
+    if (lat) {
+        s->lat_free.pop_back();
+        s->lat_busy++;
+    } else {
+        s->free_lanes.pop_back();
+    }
     r.lane = lane;
     r.out_off = off;
     r.out_granted = granted;
@@ -808,11 +1028,20 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
                hipMalloc(&s->fresh, s->nslices * 4) == hipSuccess &&
                hipMalloc(&s->sink, s->nslices * 4) == hipSuccess &&
                hipMalloc(&s->done_list, 256) == hipSuccess &&
-               hipMalloc(&s->dadm, s->nlanes * sizeof(Admit)) == hipSuccess &&
+               hipMalloc(&s->dadm, (s->nlanes + kLatStreams) * sizeof(Admit)) == hipSuccess &&
+               hipMalloc(&s->lat_state, kLatStreams * 8 * 4) == hipSuccess &&
+               hipMalloc(&s->lat_out, kLatStreams * sizeof(uint32_t *)) == hipSuccess &&
+               hipMalloc(&s->lat_left, kLatStreams * 4) == hipSuccess &&
+               hipMalloc(&s->lat_sid, kLatStreams * 4) == hipSuccess &&
+               hipMalloc(&s->lat_fresh, kLatStreams * 4) == hipSuccess &&
+               hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) == hipSuccess &&
                hipMalloc(&s->arena, budget_words * 4) == hipSuccess &&
-               hipHostMalloc((void **)&s->hadm, s->nlanes * sizeof(Admit), hipHostMallocDefault) == hipSuccess &&
+               hipHostMalloc((void **)&s->hadm, (s->nlanes + kLatStreams) * sizeof(Admit), hipHostMallocDefault) ==
+                   hipSuccess &&
                hipHostMalloc((void **)&s->hcount, 64, hipHostMallocDefault) == hipSuccess &&
-               hipHostMalloc((void **)&s->hlist, 2 * s->nlanes * 4, hipHostMallocMapped) == hipSuccess &&
+               hipHostMalloc((void **)&s->hlist, 2 * (s->nlanes + kLatStreams) * 4, hipHostMallocMapped) == hipSuccess &&
                hipHostGetDevicePointer((void **)&s->hlist_dev, s->hlist, 0) == hipSuccess &&
                hipEventCreateWithFlags(&s->ev[0], hipEventDisableTiming) == hipSuccess &&
                hipEventCreateWithFlags(&s->ev[1], hipEventDisableTiming) == hipSuccess;
@@ -827,6 +1056,8 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
     // the initial states: the registers of the given initialised instances
     int rc = mickey_state_export(init, s->pool, nullptr);
     if (rc == MICKEY_OK && (hipMemsetAsync(s->lane_left, 0, s->nlanes * 4) != hipSuccess ||
+                            hipMemsetAsync(s->lat_left, 0, kLatStreams * 4) != hipSuccess ||
+                            hipMemsetAsync(s->lat_fresh, 0, kLatStreams * 4) != hipSuccess ||
                             hipMemsetAsync(s->fresh, 0, s->nslices * 4) != hipSuccess ||
                             hipMemsetAsync(s->planes, 0, 200 * s->nslices * 4) != hipSuccess ||
                             hipDeviceSynchronize() != hipSuccess))
@@ -837,14 +1068,15 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
         return nullptr;
     }
     s->alloc.reset(budget_words);
-    s->slice_blocks.assign(s->nslices, {});
+    s->slice_blocks.assign(s->nslices + 1, {});  // + the latency streams' cache
     s->state_bits.assign(s->nstates, mickey_bits_generated(init));
     s->state_owned.assign(s->nstates, 0);
     s->chain_head.assign(s->nstates, ~0ull);
     s->chain_tail.assign(s->nstates, ~0ull);
     s->free_lanes.resize(s->nlanes);
     for (size_t i = 0; i < s->nlanes; i++) s->free_lanes[i] = (uint32_t)(s->nlanes - 1 - i);
-    s->lane_req.assign(s->nlanes, ~0ull);
+    s->lane_req.assign(s->nlanes + kLatStreams, ~0ull);
+    set_latency(s, kLatStreams, 1ull << 20, 8ull * quantum_clocks);
     ok();
     return s;
 }
@@ -887,7 +1119,7 @@ int64_t mickey_server_submit(mickey_server *s, uint32_t state_id, uint64_t nbits
 int launch_quantum(mickey_server *s, int b)
 {
     const bool staged = s->sub_blocks && s->transpose != MICKEY_TRANSPOSE_FUSED;
-    uint32_t *const list = s->hlist_dev + (size_t)b * s->nlanes;
+    uint32_t *const list = s->hlist_dev + (size_t)b * (s->nlanes + kLatStreams);
     if (!staged) {
         hipLaunchKernelGGL(quantum_kernel, dim3((unsigned)(s->nslices / 64)), dim3(64), 0, s->stream, s->planes,
                            (uint32_t)s->nslices, s->qblocks, s->lane_out, s->lane_left, s->lane_sid, s->pool,
@@ -928,18 +1160,38 @@ int mickey_server_step(mickey_server *s)
             hipSuccess)
             return check_launch("admission upload");
         hipLaunchKernelGGL(admit_kernel, dim3((s->pending + 255) / 256), dim3(256), 0, s->stream, s->dadm,
-                           s->pending, s->lane_out, s->lane_left, s->lane_sid, s->fresh);
+                           s->pending, (uint32_t)s->nlanes, s->lane_out, s->lane_left, s->lane_sid, s->fresh,
+                           s->lat_out, s->lat_left, s->lat_sid, s->lat_fresh);
         rc = check_launch("admit_kernel");
         if (rc != MICKEY_OK) return rc;
         s->pending = 0;
     }
-    // 2. launch the next quantum when any lane is occupied
-    if (s->free_lanes.size() < s->nlanes) {
+    // 2. launch the next quantum when any lane is occupied: the latency streams on the side
+    //    stream (forked after the admissions, joined before the completion count is read),
+    //    the bitsliced lanes on the server's stream, side by side
+    const bool any_bs = s->free_lanes.size() < s->nlanes, any_lat = s->lat_busy > 0;
+    if (any_bs || any_lat) {
         const int b = (int)(s->next_q & 1);
         hipLaunchKernelGGL(reset_count_kernel, dim3(1), dim3(64), 0, s->stream, s->done_count + b);
         s->launch_ns[b] = now_ns();
-        rc = launch_quantum(s, b);
-        if (rc != MICKEY_OK) return rc;
+        if (any_lat) {
+            const uint32_t n = s->lat_streams;
+            if (hipEventRecord(s->ev_fork, s->stream) != hipSuccess ||
+                hipStreamWaitEvent(s->side, s->ev_fork, 0) != hipSuccess)
+                return check_launch("latency fork");
+            hipLaunchKernelGGL(latency_quantum_kernel, dim3((n * 4 + 63) / 64), dim3(64), 0, s->side, s->lat_state, n,
+                               s->lat_words, s->lat_out, s->lat_left, s->lat_sid, s->lat_fresh, s->pool,
+                               (uint32_t)s->nlanes, s->hlist_dev + (size_t)b * (s->nlanes + kLatStreams),
+                               s->done_count + b);
+            rc = check_launch("latency_quantum_kernel");
+            if (rc != MICKEY_OK) return rc;
+            if (hipEventRecord(s->ev_join, s->side) != hipSuccess) return check_launch("latency join");
+        }
+        if (any_bs) {
+            rc = launch_quantum(s, b);
+            if (rc != MICKEY_OK) return rc;
+        }
+        if (any_lat && hipStreamWaitEvent(s->stream, s->ev_join, 0) != hipSuccess) return check_launch("latency join");
         if (hipMemcpyAsync(s->hcount + b, s->done_count + b, 4, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
             hipEventRecord(s->ev[b], s->stream) != hipSuccess)
             return check_launch("completion count");
@@ -948,7 +1200,8 @@ int mickey_server_step(mickey_server *s)
     }
     // 3. retire the previous quantum while this one runs (or the last one, if idle), then
     //    decide what the lanes it freed take next
-    if (s->next_q - s->oldest_q >= 2 || (s->next_q > s->oldest_q && s->free_lanes.size() == s->nlanes)) {
+    if (s->next_q - s->oldest_q >= 2 ||
+        (s->next_q > s->oldest_q && s->free_lanes.size() == s->nlanes && s->lat_busy == 0)) {
         rc = retire_oldest(s);
         if (rc != MICKEY_OK) return rc;
     }
@@ -1064,7 +1317,7 @@ int mickey_server_stats(const mickey_server *s, uint64_t out[11])
     if (!s || !out) return fail(MICKEY_EINVAL, "mickey_server_stats: bad argument");
     const size_t freew = s->alloc.free_words() + s->slice_cached;
     out[0] = s->ready_q.size() + s->chained + s->continuing.size();
-    out[1] = s->nlanes - s->free_lanes.size();
+    out[1] = s->nlanes - s->free_lanes.size() + s->lat_busy;
     out[2] = s->admitted;
     out[3] = s->finished;
     out[4] = s->steps;
@@ -1097,6 +1350,20 @@ int mickey_server_copy(const mickey_server *s, uint64_t id, uint32_t *dst, uint6
     if (hipMemcpyAsync(dst, src, nwords * 4, hipMemcpyDeviceToDevice, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
         return check_launch("mickey_server_copy");
+    return ok();
+}
+
+int mickey_server_set_latency(mickey_server *s, uint32_t streams, uint64_t threshold_bits,
+                              uint64_t clocks_per_quantum)
+{
+    if (!s) return fail(MICKEY_EINVAL, "mickey_server_set_latency: NULL server");
+    if (streams > kLatStreams || (streams && (clocks_per_quantum == 0 || clocks_per_quantum % 32 ||
+                                              clocks_per_quantum / 32 > 0xFFFFFFFFull)))
+        return fail(MICKEY_EINVAL, "mickey_server_set_latency: at most %u streams, clocks a positive multiple of 32",
+                    kLatStreams);
+    if (s->lat_busy || s->oldest_q != s->next_q)
+        return fail(MICKEY_EINVAL, "mickey_server_set_latency: latency streams or quanta are in flight");
+    set_latency(s, streams, threshold_bits, clocks_per_quantum);
     return ok();
 }
 

@@ -29,7 +29,7 @@ EXPORTED = [
     "mickey_server_state", "mickey_server_stream", "mickey_server_free", "mickey_server_submit_many",
     "mickey_server_release_many", "mickey_server_times_many", "mickey_server_wait",
     "mickey_server_set_chunk", "mickey_server_poll_chunks", "mickey_server_release_chunks",
-    "mickey_server_copy_chunk", "mickey_server_set_kernel",
+    "mickey_server_copy_chunk", "mickey_server_set_kernel", "mickey_server_set_latency",
     "grain_init", "grain_rekey", "grain_generate", "grain_generate_rowmajor", "grain_free", "grain_set_stream",
     "grain_num_instances", "grain_bits_generated", "grain_plane_pitch", "grain_state_export",
     "grain_state_import", "grain_sync", "grain_ops_per_clock",
@@ -146,6 +146,8 @@ def load_library():
     L.mickey_server_times_many.restype = i
     L.mickey_server_wait.argtypes = [vp]
     L.mickey_server_wait.restype = i
+    L.mickey_server_set_latency.argtypes = [vp, ctypes.c_uint32, u64, u64]
+    L.mickey_server_set_latency.restype = i
     L.mickey_server_set_kernel.argtypes = [vp, i, i]
     L.mickey_server_set_kernel.restype = i
     L.mickey_server_set_chunk.argtypes = [vp, u64]
@@ -443,6 +445,13 @@ class Server:
             raise MickeyError(L.mickey_last_error(), L.mickey_last_error_message().decode())
         self._h = ctypes.c_void_p(h)
         self.n = init.n
+        self.quantum_clocks = int(quantum_clocks)
+
+    def set_latency(self, streams: int, threshold_bits: int = 1 << 20, clocks_per_quantum: int = 0) -> None:
+        """Latency-stream routing (mickey_server_set_latency); clocks_per_quantum 0 means 8
+        quanta's worth of clocks of the server's quantum."""
+        cpq = int(clocks_per_quantum) or 8 * self.quantum_clocks
+        _check(load_library().mickey_server_set_latency(self._h, int(streams), int(threshold_bits), cpq))
 
     def set_kernel(self, schedule: int = SCHED_AUTO, transpose: int = TRANSPOSE_AUTO) -> None:
         """Kernels of the following quanta (mickey_server_set_kernel)."""

@@ -167,11 +167,14 @@ def test_submit_errors_and_2p40_limit():
     srv.close()
 
 
+@pytest.mark.parametrize("latency", [False, True], ids=["bit-lanes", "latency-streams"])
 @pytest.mark.parametrize("kernel", KERNELS, ids=KERNEL_IDS)
-def test_chunked_delivery_continues_states_exactly(kernel):
+def test_chunked_delivery_continues_states_exactly(kernel, latency):
     keys, ivs, ivb, init = make_pool(7, 120)
     # budget 4 KiB: far smaller than several requests below, which stream through it
     srv = server(init, kernel, nslices=64, quantum_clocks=64, budget_bytes=4096)
+    if latency:  # what is left of requests of 100+ words takes one of 8 latency streams
+        srv.set_latency(8, threshold_bits=32 * 100, clocks_per_quantum=32 * 3)
     init.close()
     rng = np.random.default_rng(8)
     plan = []  # (state, bits, chunk bytes)
@@ -294,4 +297,56 @@ def test_set_kernel_errors():
         with pytest.raises(mickey.MickeyError) as e:
             srv.set_kernel(sched, tp)
         assert e.value.code == mickey.EINVAL
+    srv.close()
+
+
+@pytest.mark.parametrize("streams", [5, 4096])
+def test_latency_streams_continue_states(streams):
+    """Size-aware routing: requests with at least 20 words left run on latency streams
+    (5 of them, so many overflow to bit lanes, or 4096, so none do); a state's successive
+    requests alternate between the two kinds of lane and must still continue exactly."""
+    keys, ivs, ivb, init = make_pool(21, 300)
+    srv = mickey.Server(init, nslices=64, quantum_clocks=64, budget_bytes=1 << 22)
+    srv.set_latency(streams, threshold_bits=32 * 20, clocks_per_quantum=32 * 5)
+    init.close()
+    rng = np.random.default_rng(22)
+    sids = rng.integers(0, 300, 400)
+    sids[:8] = [7, 7, 7, 7, 8, 8, 8, 299]
+    lengths = 32 * rng.integers(1, 120, 400)
+    lengths[:8] = [32 * 30, 32 * 3, 32 * 45, 32 * 1, 32 * 21, 32 * 20, 32 * 19, 32 * 100]
+    ids = [srv.submit(int(s), int(nb)) for s, nb in zip(sids, lengths)]
+    assert sorted(drain(srv)) == sorted(ids)
+    hist = {}
+    for rid, s, nb in zip(ids, sids, lengths):
+        hist.setdefault(int(s), []).append((rid, int(nb)))
+    for s in list(hist)[:80] + [7, 8, 299]:
+        reqs = hist[s]
+        want = oracle_history(keys, ivs, ivb, s, [nb for _, nb in reqs])
+        for (rid, nb), w in zip(reqs, want):
+            assert (fetch(srv, rid, nb) == w).all(), (s, rid)
+        assert srv.state_bits(s) == sum(nb for _, nb in reqs)
+    t = [srv.times(r)[2] for r, _ in hist[7]]
+    assert t == sorted(t)
+    srv.close()
+
+
+def test_set_latency_errors():
+    keys, ivs, ivb, init = make_pool(23, 8, mixed=False)
+    srv = mickey.Server(init, nslices=64, quantum_clocks=32, budget_bytes=1 << 16)
+    init.close()
+    L = mickey.load_library()
+    assert L.mickey_server_set_latency(srv._h, 16385, 1 << 20, 256) == mickey.EINVAL  # too many streams
+    assert L.mickey_server_set_latency(srv._h, 8, 1 << 20, 33) == mickey.EINVAL     # not whole words
+    assert L.mickey_server_set_latency(srv._h, 8, 1 << 20, 0) == mickey.EINVAL
+    srv.set_latency(8, threshold_bits=64, clocks_per_quantum=64)
+    rid = srv.submit(0, 32 * 50)
+    srv.step()  # now a latency stream is busy
+    assert L.mickey_server_set_latency(srv._h, 0, 0, 0) == mickey.EINVAL
+    drain(srv)
+    srv.wait()
+    srv.set_latency(0)  # off: everything takes bit lanes
+    rid2 = srv.submit(0, 32 * 50)
+    drain(srv)
+    want = oracle_history(keys, ivs, None, 0, [32 * 50, 32 * 50])
+    assert (fetch(srv, rid, 32 * 50) == want[0]).all() and (fetch(srv, rid2, 32 * 50) == want[1]).all()
     srv.close()
