@@ -198,7 +198,8 @@ def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 
     """10,000 fresh requests (seed 4): IV lengths 0..80, lengths log-uniform in
     [2^8, 2^24) bits; one persistent work-queue launch replayed from a HIP graph,
     autotuned; compared with per-request plain launches (timed on a sample of requests
-    and extrapolated linearly in length) and with the critical-path bound."""
+    and extrapolated linearly in length) and with the critical-path bound: the longest
+    request alone in latency mode."""
     import tempfile
     keys, ivs, ivb, nbits = synth.batch_requests(4, 10000)
     n = len(nbits)
@@ -253,6 +254,24 @@ def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 
     serial_ms = float(np.sum(icpt + slope * nbits.astype(np.float64)))
     lmax = int(nbits.max())
     bound_ms = float(icpt + slope * lmax)  # one lane running the longest request alone
+    # the longest request alone in latency mode (a batch of one, routed there): the
+    # critical path of any schedule of this batch on this engine
+    il = int(np.argmax(nbits))
+    b1 = mickey.Batch(1)
+    buf1 = torch.empty(lmax // 32, dtype=torch.int32, device="cuda")
+    b1.set(dk[il:il + 1], dv[il:il + 1], db[il:il + 1], nbits[il:il + 1], [buf1.data_ptr()])
+    b1.set_latency_threshold(1)
+    bs1 = torch.cuda.ExternalStream(b1.stream_handle)
+    lat_alone = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        e0.record(bs1)
+        b1.run()
+        e1.record(bs1)
+        b1.sync()
+        lat_alone.append(e0.elapsed_time(e1))
+    b1.close()
+    lat_bound_ms = float(lat_alone[-1])
     return {"workload": "10,000 fresh requests (splitmix64 seed 4), IV lengths 0..80, lengths log-uniform in "
                         "[2^8, 2^24) bits, row-major u32 outputs, one persistent launch (HIP graph)",
             "requests": n, "total_bits": total_bits, "batch_ms": round(batch_ms, 2),
@@ -265,9 +284,10 @@ def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 
             "critical_path": {"longest_bits": lmax,
                               "bitsliced_bound_ms": round(bound_ms, 2),
                               "bitsliced_only_over_bound": round(bs_only_ms / bound_ms, 4),
-                              "latency_mode_bound_ms": round(bound_ms * routing[2], 2),
-                              "batch_over_latency_bound": round(batch_ms / (bound_ms * routing[2]), 4),
-                              "clock_ns_single_bitsliced_lane": round(slope * 1e6, 2)},
+                              "latency_mode_bound_ms": round(lat_bound_ms, 2),
+                              "batch_over_latency_bound": round(batch_ms / lat_bound_ms, 4),
+                              "clock_ns_single_bitsliced_lane": round(slope * 1e6, 2),
+                              "clock_ns_single_latency_request": round(lat_bound_ms * 1e6 / lmax, 2)},
             "per_request_plain": {"sampled": len(ts), "fit_ms": [round(icpt, 4), round(slope * 1e6, 4)],
                                   "fit_units": ["ms", "ns per bit"], "extrapolated_serial_ms": round(serial_ms, 1),
                                   "batch_speedup": round(serial_ms / batch_ms, 1)}}

@@ -74,18 +74,20 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2, 2))
     }
 }
 
-// Latency mode: one request per lane, word-parallel clock.  Lane i runs request
-// order[i]: the same input string as the bitsliced staging (IV right-aligned to clock
-// 80, then the key, then 100 zero clocks), lanes with IV length L idle for 80 - L
-// clocks, then 32 clocks per output word (first bit in the MSB).
+// Latency mode: one request per quad of lanes.  Every lane of quad i runs request
+// order[i]'s initialisation with the one-lane word-parallel clock (the same input string
+// as the bitsliced staging: IV right-aligned to clock 80, then the key, then 100 zero
+// clocks; lanes with IV length L idle for 80 - L clocks); then lane q keeps word q of R
+// and S and the quad generates with the four-lane clock, 32 clocks per output word
+// (first bit in the MSB, stored by lane 0).
 __global__ __launch_bounds__(64) void latency_kernel(const uint8_t *__restrict__ keys, const uint8_t *__restrict__ ivs,
                                                      const uint8_t *__restrict__ iv_bits,
                                                      const uint32_t *__restrict__ order, uint32_t nlanes,
                                                      uint32_t *const *__restrict__ lane_out,
                                                      const uint32_t *__restrict__ lane_words)
 {
-    const uint32_t i = blockIdx.x * 64u + threadIdx.x;
-    if (i >= nlanes) return;
+    const uint32_t t = blockIdx.x * 64u + threadIdx.x, i = t >> 2, q = t & 3u;
+    if (i >= nlanes) return;  // whole quads
     const uint32_t req = order[i];
     const uint8_t *k = keys + 10ull * req;
     const uint8_t *v = ivs + 10ull * req;
@@ -107,32 +109,35 @@ __global__ __launch_bounds__(64) void latency_kernel(const uint8_t *__restrict__
     const uint32_t d = 80u - L;
     WState x;
 #pragma unroll
-    for (int q = 0; q < 4; q++) x.r[q] = x.s[q] = 0u;
+    for (int j = 0; j < 4; j++) x.r[j] = x.s[j] = 0u;
 #pragma unroll
     for (int c = 0; c < 5; c++) {  // the 160 input clocks, 32 per input word
         for (uint32_t b = 0; b < 32u; b += 4) {
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-                const uint32_t t = 32u * c + b + u;
+                const uint32_t tt = 32u * c + b + u;
                 const uint32_t in_m = (uint32_t)((int32_t)(w[c] << (b + u)) >> 31);
-                if (t >= d) wclock<true>(x, in_m);  // lanes with short IVs start late
+                if (tt >= d) wclock<true>(x, in_m);  // lanes with short IVs start late
             }
         }
     }
-    for (uint32_t t = 0; t < 100u; t += 4) {  // preclocks
+    for (uint32_t tt = 0; tt < 100u; tt += 4) {  // preclocks
 #pragma unroll
         for (int u = 0; u < 4; u++) wclock<true>(x, 0u);
     }
+    uint32_t r = pick4(q, x.r[0], x.r[1], x.r[2], x.r[3]);
+    uint32_t s = pick4(q, x.s[0], x.s[1], x.s[2], x.s[3]);
+    const QuadMasks m = quad_masks(q);
     uint32_t *out = lane_out[i];
     const uint32_t nw = lane_words[i];
     for (uint32_t j = 0; j < nw; j++) {
         uint32_t acc = 0;
 #pragma unroll
         for (int b = 0; b < 32; b++) {
-            acc = __builtin_amdgcn_alignbit(x.r[0] ^ x.s[0], acc, 1);  // z enters at bit 31
-            wclock<false>(x, 0u);
+            acc = __builtin_amdgcn_alignbit(r ^ s, acc, 1);  // z = r_0 ^ s_0 (lane 0) enters at bit 31
+            quad_clock(r, s, m);
         }
-        store_global(out + j, __builtin_bitreverse32(acc));  // first bit of the word in the MSB
+        if (q == 0) store_global(out + j, __builtin_bitreverse32(acc));  // first bit of the word in the MSB
     }
 }
 
@@ -206,7 +211,7 @@ struct mickey_batch {
 
 namespace {
 
-constexpr size_t kMaxLatencyLanes = 65536;  // 1024 waves of word-parallel lanes
+constexpr size_t kMaxLatencyLanes = 16384;  // 1024 waves of four-lane latency requests
 
 void drop_graph(mickey_batch *b)
 {
@@ -313,7 +318,7 @@ int launch_bitsliced(mickey_batch *b, const Variant &v)
 
 int launch_latency(mickey_batch *b, hipStream_t s)
 {
-    hipLaunchKernelGGL(latency_kernel, dim3((unsigned)((b->nlat + 63) / 64)), dim3(64), 0, s, b->keys, b->ivs,
+    hipLaunchKernelGGL(latency_kernel, dim3((unsigned)((4 * b->nlat + 63) / 64)), dim3(64), 0, s, b->keys, b->ivs,
                        b->iv_bits, b->lat_order, (uint32_t)b->nlat, b->lat_out, b->lat_words);
     return check_launch("latency_kernel");
 }
