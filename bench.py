@@ -116,8 +116,7 @@ def bench_rowmajor(torch, mickey, synth, reps: int = 3):
         if name == "auto":
             res.update(leg)
             res["path"] = ("four-wave split schedule (%d waves) into 4096-clock bit-plane chunks (two 512 MiB "
-                           "buffers), tiled transpose on a second stream overlapping the next chunk"
-                           % (4 * (n // 32 // 64)))
+                           "buffers), each followed by the tiled transpose to u32 + f32 rows" % (4 * (n // 32 // 64)))
         else:
             res[name] = leg
     return res
