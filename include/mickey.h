@@ -226,7 +226,7 @@ int mickey_batch_autotune(mickey_batch *b, uint64_t cap_bits, const char *cache_
  * request per four lanes, words of the registers spread over the lanes: ~10x more VALU
  * work per bit, but a lone instance advances several times faster), the rest bitsliced;
  * both run concurrently in the same graph and give identical words.  0 (the default)
- * sets the threshold automatically to L_max * r, r being the tuned ratio of the two
+ * sets the threshold automatically to 3/4 * L_max * r, r being the tuned ratio of the two
  * engines' clock times, so that the bitsliced part finishes before the longest request;
  * UINT64_MAX turns latency mode off.  At most 16384 requests take latency mode. */
 int mickey_batch_set_latency_threshold(mickey_batch *b, uint64_t bits);

@@ -222,10 +222,12 @@ void drop_graph(mickey_batch *b)
 }
 
 // Size-aware routing: requests of at least `threshold` bits run in latency mode (one
-// lane each, word-parallel clock), the others bitsliced (32 per slice), each part
-// sorted longest first.  The automatic threshold is L_max * (latency-lane clock /
-// bitsliced clock): shorter requests finish in bitsliced mode before the longest
-// request finishes in latency mode.  At most kMaxLatencyLanes requests take latency mode.
+// quad of lanes each), the others bitsliced (32 per slice), each part sorted longest
+// first.  The automatic threshold is 3/4 * L_max * (latency clock / bitsliced clock):
+// shorter requests finish in bitsliced mode before the longest request finishes in
+// latency mode (at the full ratio the persistent bitsliced kernel, with its task tail,
+// measured 8% longer than the longest latency request).  At most kMaxLatencyLanes
+// requests take latency mode.
 void route(mickey_batch *b, const std::vector<uint64_t> &nbits, uint64_t setting)
 {
     const size_t n = nbits.size();
@@ -233,7 +235,7 @@ void route(mickey_batch *b, const std::vector<uint64_t> &nbits, uint64_t setting
     for (uint64_t v : nbits) lmax = std::max(lmax, v);
     uint64_t th = ~0ull;
     if (setting == 0) {
-        const uint64_t auto_th = (uint64_t)((double)lmax * b->lat_ratio);
+        const uint64_t auto_th = (uint64_t)(0.75 * (double)lmax * b->lat_ratio);
         th = std::max<uint64_t>(auto_th, 1u << 12);
     } else if (setting != ~0ull) {
         th = setting;
