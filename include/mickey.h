@@ -320,9 +320,10 @@ int mickey_server_set_chunk(mickey_server *s, uint64_t chunk_bytes);
  *              and a tiled transpose writes each request's words as whole lines;
  *              MICKEY_TRANSPOSE_AUTO: STAGED when the buffer exists (it does unless one
  *              32-clock launch of planes exceeds 512 MiB).
- *   schedule   for staged quanta, MICKEY_SCHED_ONE_WAVE / _SPLIT / _AUTO as for
- *              mickey_set_schedule (AUTO: split up to one one-wave wave per SIMD).
- * MICKEY_EINVAL for FUSED with SPLIT, or STAGED / SPLIT without the buffer. */
+ *   schedule   for staged quanta, MICKEY_SCHED_ONE_WAVE / _SPLIT / _SPLIT4 / _AUTO as
+ *              for mickey_set_schedule (AUTO: the four-wave split below two one-wave
+ *              waves per SIMD).
+ * MICKEY_EINVAL for FUSED with a split schedule, or STAGED / a split without the buffer. */
 int mickey_server_set_kernel(mickey_server *s, int schedule, int transpose);
 
 /* Latency streams (the paper's Sec. VI: delay is the GPU's drawback): the part of a
@@ -359,8 +360,10 @@ int mickey_server_release(mickey_server *s, uint64_t id);
 /* [0] waiting (including chunked requests between two chunks), [1] running, [2] admitted,
  * [3] finished, [4] steps, [5] quantum time in
  * ns (launch to retirement), [6] keystream bits delivered, [7] free budget in 32-bit
- * words, [8] host ns blocked on quanta, [9] host ns retiring, [10] host ns admitting. */
-int mickey_server_stats(const mickey_server *s, uint64_t out[11]);
+ * words, [8] host ns blocked on quanta, [9] host ns retiring, [10] host ns admitting,
+ * [11] device ns of the quanta (each from its first kernel's start to its completion count,
+ * timed with HIP events; gaps between quanta are not counted). */
+int mickey_server_stats(const mickey_server *s, uint64_t out[12]);
 
 /* Device pointer to resident state `state_id` (25 bytes) and its bit counter. */
 int mickey_server_state(const mickey_server *s, uint32_t state_id, const uint8_t **packed, uint64_t *bits);

@@ -325,6 +325,138 @@ __device__ __forceinline__ void split_s_clock(Regs<1> &x, Word<1> &r33, SplitLds
 }
 
 // ---------------------------------------------------------------------------------
+// Four-wave split clock (one workgroup of four waves per 64 slices): wave 0 keeps
+// r_0..r_49, wave 1 r_50..r_99, wave 2 s_0..s_49, wave 3 s_50..s_99.  Each position's
+// next value is a function of the current state (r_next / s_next), so each wave first
+// computes the values the others need for the next clock, writes them to a
+// double-buffered LDS slot, passes the clock's one barrier, issues its reads, and then
+// computes the rest of its half-register.  Exchanged per clock (next-state values): r_49
+// (to wave 1), r_33 (to the S waves, for c_S), r_99 and r_67 (to wave 0, for fb_R and
+// c_R), s_34 (to the R waves), s_0 (to wave 0, for z), s_49 (to wave 3), s_50, s_99 and
+// s_67 (to wave 2).
+enum : int { kX_R49, kX_R33, kX_R99, kX_R67, kX_S49, kX_S34, kX_S0, kX_S50, kX_S99, kX_S67, kXSlots };
+struct Split4Lds {
+    uint32_t v[2][kXSlots][64];
+};
+
+constexpr bool ex3(int i, int a, int b, int c) { return i == a || i == b || i == c; }
+
+// n.r[LO + j] for j < N, except positions A, B, C
+template <int LO, int A, int B, int C, int... J>
+__device__ __forceinline__ void r_next_range(Regs<1> &n, const Regs<1> &x, const Word<1> &cr, const Word<1> &fbr,
+                                             std::integer_sequence<int, J...>)
+{
+    ((ex3(LO + J, A, B, C) ? void() : void(n.r[LO + J] = r_next<LO + J, 1>(x, cr, fbr))), ...);
+}
+template <int LO, int A, int B, int C, int... J>
+__device__ __forceinline__ void s_next_range(Regs<1> &n, const Regs<1> &x, const Word<1> &fbs, const Word<1> &g0,
+                                             const Word<1> &g1, std::integer_sequence<int, J...>)
+{
+    ((ex3(LO + J, A, B, C) ? void() : void(n.s[LO + J] = s_next<LO + J, 1>(x, fbs, g0, g1))), ...);
+}
+
+struct S4In {  // next-clock values a wave receives
+    Word<1> a, b, c, d;
+};
+
+// wave 0: in = {r_99, r_67, s_34, s_0} of the current state
+template <int PH>
+__device__ __forceinline__ void s4_clock_rlo(Regs<1> &x, S4In &in, Split4Lds &xl, uint32_t lane)
+{
+    const Word<1> cr = in.c ^ in.b, fbr = in.a;
+    Regs<1> n;
+    n.r[49] = r_next<49, 1>(x, cr, fbr);
+    n.r[33] = r_next<33, 1>(x, cr, fbr);
+    xl.v[PH][kX_R49][lane] = n.r[49].w[0];
+    xl.v[PH][kX_R33][lane] = n.r[33].w[0];
+    lds_barrier();
+    in.a.w[0] = xl.v[PH][kX_R99][lane];
+    in.b.w[0] = xl.v[PH][kX_R67][lane];
+    in.c.w[0] = xl.v[PH][kX_S34][lane];
+    in.d.w[0] = xl.v[PH][kX_S0][lane];
+    __builtin_amdgcn_sched_barrier(0);
+    r_next_range<0, 49, 33, -1>(n, x, cr, fbr, std::make_integer_sequence<int, 50>{});
+#pragma unroll
+    for (int j = 0; j < 50; j++) x.r[j] = n.r[j];
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// wave 1: in = {s_34}; x.r[49] holds the current r_49
+template <int PH>
+__device__ __forceinline__ void s4_clock_rhi(Regs<1> &x, S4In &in, Split4Lds &xl, uint32_t lane)
+{
+    const Word<1> cr = in.a ^ x.r[67], fbr = x.r[99];
+    Regs<1> n;
+    n.r[99] = r_next<99, 1>(x, cr, fbr);
+    n.r[67] = r_next<67, 1>(x, cr, fbr);
+    xl.v[PH][kX_R99][lane] = n.r[99].w[0];
+    xl.v[PH][kX_R67][lane] = n.r[67].w[0];
+    lds_barrier();
+    Word<1> r49;
+    r49.w[0] = xl.v[PH][kX_R49][lane];
+    in.a.w[0] = xl.v[PH][kX_S34][lane];
+    __builtin_amdgcn_sched_barrier(0);
+    r_next_range<50, 99, 67, -1>(n, x, cr, fbr, std::make_integer_sequence<int, 50>{});
+#pragma unroll
+    for (int j = 50; j < 100; j++) x.r[j] = n.r[j];
+    x.r[49] = r49;
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// wave 2: in = {s_99, s_67, r_33}; x.s[50] holds the current s_50
+template <int PH>
+__device__ __forceinline__ void s4_clock_slo(Regs<1> &x, S4In &in, Split4Lds &xl, uint32_t lane)
+{
+    const Word<1> cs = in.b ^ in.c, fbs = in.a;
+    const Word<1> g1 = fbs & cs;
+    const Word<1> g0 = fbs ^ g1;
+    Regs<1> n;
+    n.s[49] = s_next<49, 1>(x, fbs, g0, g1);
+    n.s[34] = s_next<34, 1>(x, fbs, g0, g1);
+    xl.v[PH][kX_S49][lane] = n.s[49].w[0];
+    xl.v[PH][kX_S34][lane] = n.s[34].w[0];
+    xl.v[PH][kX_S0][lane] = fbs.w[0];  // the next s_0
+    lds_barrier();
+    Word<1> s50;
+    s50.w[0] = xl.v[PH][kX_S50][lane];
+    in.a.w[0] = xl.v[PH][kX_S99][lane];
+    in.b.w[0] = xl.v[PH][kX_S67][lane];
+    in.c.w[0] = xl.v[PH][kX_R33][lane];
+    __builtin_amdgcn_sched_barrier(0);
+    s_next_range<0, 49, 34, -1>(n, x, fbs, g0, g1, std::make_integer_sequence<int, 50>{});
+#pragma unroll
+    for (int j = 0; j < 50; j++) x.s[j] = n.s[j];
+    x.s[50] = s50;
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// wave 3: in = {r_33}; x.s[49] holds the current s_49
+template <int PH>
+__device__ __forceinline__ void s4_clock_shi(Regs<1> &x, S4In &in, Split4Lds &xl, uint32_t lane)
+{
+    const Word<1> cs = x.s[67] ^ in.a, fbs = x.s[99];
+    const Word<1> g1 = fbs & cs;
+    const Word<1> g0 = fbs ^ g1;
+    Regs<1> n;
+    n.s[50] = s_next<50, 1>(x, fbs, g0, g1);
+    n.s[99] = s_next<99, 1>(x, fbs, g0, g1);
+    n.s[67] = s_next<67, 1>(x, fbs, g0, g1);
+    xl.v[PH][kX_S50][lane] = n.s[50].w[0];
+    xl.v[PH][kX_S99][lane] = n.s[99].w[0];
+    xl.v[PH][kX_S67][lane] = n.s[67].w[0];
+    lds_barrier();
+    Word<1> s49;
+    s49.w[0] = xl.v[PH][kX_S49][lane];
+    in.a.w[0] = xl.v[PH][kX_R33][lane];
+    __builtin_amdgcn_sched_barrier(0);
+    s_next_range<50, 50, 99, 67>(n, x, fbs, g0, g1, std::make_integer_sequence<int, 50>{});
+#pragma unroll
+    for (int j = 50; j < 100; j++) x.s[j] = n.s[j];
+    x.s[49] = s49;
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// ---------------------------------------------------------------------------------
 // a5, staged: tiled transpose of bit-planes (plane t: one word per slice, nslices words)
 // into per-instance row words.  A 256-thread workgroup takes a tile of kTpSlices slices
 // (512 instances) x kTpClocks clocks: it reads the tile's plane words into LDS, turns
@@ -342,8 +474,11 @@ static_assert(32 * kTpSlices * kTpBlocks <= kTpLdsWords, "row staging reuses the
 // nb (<= kTpBlocks) blocks from clock t0, slices s0 .. s0+15 (those past nslices read a
 // copy of the last pair and must not be written out; nslices is even).  Ends with the
 // rows in LDS after a barrier.
+// `publish` runs after the plane reads are issued and before the first barrier: a caller's
+// own LDS writes there are visible to the whole block afterwards.
+template <class Publish>
 __device__ __forceinline__ void tile_to_rows(uint32_t *lds, const uint32_t *__restrict__ planes, uint32_t nslices,
-                                             uint32_t s0, uint32_t t0, uint32_t nb, uint32_t tid)
+                                             uint32_t s0, uint32_t t0, uint32_t nb, uint32_t tid, Publish &&publish)
 {
     {  // each lane loads a pair of slice words of one plane; 32 planes (one block) per pass
         const uint32_t pr = tid & 7u, b = tid >> 3;
@@ -351,12 +486,24 @@ __device__ __forceinline__ void tile_to_rows(uint32_t *lds, const uint32_t *__re
         if (sp >= nslices) sp = nslices - 2u;
         const uint32_t *src = planes + (size_t)(t0 + b) * nslices + sp;
         uint32_t *dst = lds + b * kTpSlices + 2u * pr;
-        for (uint32_t q = 0; q < nb; q++) {
+        uint32_t q = 0;
+        for (; q + 16u <= nb; q += 16u) {  // sixteen loads in flight before the first LDS write
+            uint2 v[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) v[k] = *(const uint2 *)(src + (size_t)(q + k) * 32u * nslices);
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                dst[(q + k) * kTpInStride] = v[k].x;
+                dst[(q + k) * kTpInStride + 1] = v[k].y;
+            }
+        }
+        for (; q < nb; q++) {
             const uint2 v = *(const uint2 *)(src + (size_t)q * 32u * nslices);
             dst[q * kTpInStride] = v.x;
             dst[q * kTpInStride + 1] = v.y;
         }
     }
+    publish();
     __syncthreads();
     // item (slice s, block q): row 31-b holds clock 32q+b, so the transposed word l is
     // instance l's word with bit 31-b = clock b

@@ -126,31 +126,38 @@ __device__ __forceinline__ void write_back_lane(const Regs<1> &x, uint32_t l, ui
     for (int b = 0; b < 25; b++) dst[b] = (uint8_t)(w[b >> 2] >> (24 - 8 * (b & 3)));
 }
 
-// Half of write_back_lane, for the split schedule where one wave holds R and another S:
-// R is bytes 0..11 and the high nibble of byte 12, S the low nibble of byte 12 and bytes
-// 13..24.  The shared byte is updated with two atomics on its aligned word, touching
-// only this half's nibble (the other wave and the neighbouring states own the rest).
-template <bool R>
-__device__ __forceinline__ void write_back_half(const Regs<1> &x, uint32_t l, uint8_t *dst)
+// Bits J0..J1-1 of write_back_lane (0..99: r_j, 100..199: s_{j-100}), for the split
+// schedules where each wave holds part of the registers.  Bytes wholly inside the range
+// are stored; a byte shared with another part (at most one at each end) is updated with
+// two atomics on its aligned word that touch only this part's bits (the other waves and
+// the neighbouring states own the rest).
+template <int J0, int J1>
+__device__ __forceinline__ void write_back_range(const Regs<1> &x, uint32_t l, uint8_t *dst)
 {
-    constexpr int J0 = R ? 0 : 100;
     uint32_t w[7];
 #pragma unroll
     for (int k = 0; k < 7; k++) w[k] = 0u;
 #pragma unroll
-    for (int j = J0; j < J0 + 100; j++) {
+    for (int j = J0; j < J1; j++) {
         const uint32_t v = j < 100 ? x.r[j].w[0] : x.s[j - 100].w[0];
         w[j >> 5] |= ((v >> l) & 1u) << (31 - (j & 31));
     }
 #pragma unroll
-    for (int b = R ? 0 : 13; b < (R ? 12 : 25); b++) dst[b] = (uint8_t)(w[b >> 2] >> (24 - 8 * (b & 3)));
-    const uint32_t mask = R ? 0xF0u : 0x0Fu;
-    const uint32_t v12 = (w[3] >> 24) & mask;
-    const uintptr_t a = (uintptr_t)(dst + 12);
-    uint32_t *word = (uint32_t *)(a & ~(uintptr_t)3);
-    const uint32_t sh = (uint32_t)(a & 3u) * 8u;
-    atomicAnd(word, ~(mask << sh));
-    atomicOr(word, v12 << sh);
+    for (int b = J0 / 8; b < (J1 + 7) / 8; b++) {
+        const uint32_t v = (w[b >> 2] >> (24 - 8 * (b & 3))) & 0xFFu;
+        const int lo = 8 * b > J0 ? 8 * b : J0, hi = 8 * b + 8 < J1 ? 8 * b + 8 : J1;
+        if (lo == 8 * b && hi == 8 * b + 8) {
+            dst[b] = (uint8_t)v;
+        } else {
+            uint32_t mask = 0;
+            for (int j = lo; j < hi; j++) mask |= 1u << (7 - (j - 8 * b));
+            const uintptr_t a = (uintptr_t)(dst + b);
+            uint32_t *word = (uint32_t *)(a & ~(uintptr_t)3);
+            const uint32_t sh = (uint32_t)(a & 3u) * 8u;
+            atomicAnd(word, ~(mask << sh));
+            atomicOr(word, (v & mask) << sh);
+        }
+    }
 }
 
 // One quantum of nblocks*32 clocks on every slice with an occupied lane bit.  Each lane's
@@ -435,16 +442,23 @@ struct mickey_server {
     hipStream_t side = nullptr;  // latency streams run here, beside the bitsliced quantum
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     uint32_t *done_list = nullptr, *done_count = nullptr;
-    Admit *dadm = nullptr;
     uint32_t *arena = nullptr;
     serve_arena::Arena alloc;
     // host side
-    Admit *hadm = nullptr;          // pinned
+    // Admissions, in pinned mapped memory that admit_kernel reads directly (the stream holds
+    // kernels and events only).  Two buffers: the kernel reading one may still be queued
+    // behind the quantum in flight while the next admissions are written to the other.
+    Admit *hadm_buf[2] = {nullptr, nullptr};
+    Admit *hadm_dev[2] = {nullptr, nullptr};  // device views
+    int adm_b = 0;                            // the buffer being filled
+    Admit *hadm = nullptr;                    // == hadm_buf[adm_b]
     // Two quanta can be in flight: quantum q uses completion buffer q & 1.
-    uint32_t *hcount = nullptr;     // pinned [2]: completions of each in-flight quantum
+    uint32_t *hcount = nullptr;     // pinned, mapped [2]: completions of each in-flight quantum
+    uint32_t *hcount_dev = nullptr; // device view of hcount
     uint32_t *hlist = nullptr;      // pinned, mapped [2][nlanes]: completed lanes
     uint32_t *hlist_dev = nullptr;  // device view of hlist
     hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev_start[2] = {nullptr, nullptr};  // before each quantum's first kernel
     uint64_t launch_ns[2] = {0, 0};
     uint64_t next_q = 0, oldest_q = 0;  // quanta [oldest_q, next_q) are in flight
     uint32_t pending = 0;               // admissions decided, not yet enqueued
@@ -469,6 +483,7 @@ struct mickey_server {
     std::vector<uint64_t> free_slots;
     uint64_t steps = 0, quanta_ns = 0, admitted = 0, finished = 0, bits_done = 0;
     uint64_t ns_wait = 0, ns_retire = 0, ns_admit = 0;  // host time spent in each part
+    uint64_t ns_gpu = 0;  // device time of the quanta, first kernel to completion count
 };
 
 namespace {
@@ -478,15 +493,16 @@ void destroy(mickey_server *s)
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (void *p : {(void *)s->pool, (void *)s->planes, (void *)s->lane_out, (void *)s->lane_left,
-                    (void *)s->lane_sid, (void *)s->fresh, (void *)s->sink, (void *)s->done_list, (void *)s->dadm,
+                    (void *)s->lane_sid, (void *)s->fresh, (void *)s->sink, (void *)s->done_list,
                     (void *)s->arena, (void *)s->zplanes, (void *)s->row_dst, (void *)s->row_cnt,
                     (void *)s->lat_state, (void *)s->lat_out, (void *)s->lat_left, (void *)s->lat_sid,
                     (void *)s->lat_fresh})
         if (p) (void)hipFree(p);
-    if (s->hadm) (void)hipHostFree(s->hadm);
+    for (Admit *h : s->hadm_buf)
+        if (h) (void)hipHostFree(h);
     if (s->hcount) (void)hipHostFree(s->hcount);
     if (s->hlist) (void)hipHostFree(s->hlist);
-    for (hipEvent_t e : s->ev)
+    for (hipEvent_t e : {s->ev[0], s->ev[1], s->ev_start[0], s->ev_start[1]})
         if (e) (void)hipEventDestroy(e);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     if (s->side) {
@@ -660,7 +676,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 const uint32_t finished = ending_lanes(lane_left, g, active, blk, next_end);
                 for (uint32_t l = 0; l < 32; l++) {
                     if ((finished >> l) & 1u) {
-                        write_back_half<true>(x, l, pool + 25ull * lane_sid[g * 32u + l]);
+                        write_back_range<0, 100>(x, l, pool + 25ull * lane_sid[g * 32u + l]);
                         done_list[atomicAdd(done_count, 1u)] = g * 32u + l;
                     }
                 }
@@ -693,7 +709,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             if (blk + 1u == next_end) {
                 const uint32_t finished = ending_lanes(lane_left, g, active, blk, next_end);
                 for (uint32_t l = 0; l < 32; l++)
-                    if ((finished >> l) & 1u) write_back_half<false>(x, l, pool + 25ull * lane_sid[g * 32u + l]);
+                    if ((finished >> l) & 1u) write_back_range<100, 200>(x, l, pool + 25ull * lane_sid[g * 32u + l]);
                 active &= ~finished;
             }
         }
@@ -705,27 +721,182 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
 }
 
+// Four-wave staged quantum: the four-wave split of the plain path (wave 0: r_0..r_49 and
+// the keystream, wave 1: r_50..r_99, wave 2: s_0..s_49, wave 3: s_50..s_99) with the lane
+// bookkeeping of quantum_split_kernel: every wave sees the same lane_left values (wave 0
+// changes them only after a final barrier), so all four run the same blocks and pass the
+// same barriers; each gathers and packs back its own quarter of a lane's state.
+template <int ROLE>
+__device__ __forceinline__ void serve4_run(uint32_t *__restrict__ planes, size_t pitch, uint32_t voff, uint32_t g,
+                                           uint32_t lane, uint32_t nblocks, uint32_t active, uint32_t next_end,
+                                           uint32_t fr0, uint32_t **lane_out, uint32_t *__restrict__ lane_left,
+                                           const uint32_t *__restrict__ lane_sid, uint8_t *__restrict__ pool,
+                                           uint32_t *__restrict__ fresh, uint32_t *__restrict__ zplanes,
+                                           uint32_t **row_dst, uint32_t *__restrict__ row_cnt,
+                                           uint32_t *__restrict__ done_list, uint32_t *__restrict__ done_count,
+                                           Split4Lds &xl)
+{
+    constexpr bool kR = ROLE < 2;
+    constexpr int j0 = ROLE == 0 || ROLE == 2 ? 0 : 50;  // first position of the quarter
+    constexpr int base = kR ? 0 : 100;                  // r or s planes / packed bits
+    constexpr int J0 = base + j0, J1 = J0 + 50;        // the quarter's packed bits
+    Regs<1> x;
+    S4In in;
+#pragma unroll
+    for (int j = 0; j < 50; j++) {
+        const Word<1> v = ld_word<1>((const char *)planes + (size_t)(base + j0 + j) * pitch + voff);
+        if constexpr (kR) x.r[j0 + j] = v;
+        else x.s[j0 + j] = v;
+    }
+    for (uint32_t fr = fr0; fr; fr &= fr - 1u) {
+        const uint32_t l = (uint32_t)__builtin_ctz(fr);
+        gather_lane<J0, J1>(x, l, pool + 25ull * lane_sid[g * 32u + l]);
+    }
+    if constexpr (ROLE == 0) {
+        xl.v[0][kX_R49][lane] = x.r[49].w[0];
+        xl.v[0][kX_R33][lane] = x.r[33].w[0];
+    } else if constexpr (ROLE == 1) {
+        xl.v[0][kX_R99][lane] = x.r[99].w[0];
+        xl.v[0][kX_R67][lane] = x.r[67].w[0];
+    } else if constexpr (ROLE == 2) {
+        xl.v[0][kX_S49][lane] = x.s[49].w[0];
+        xl.v[0][kX_S34][lane] = x.s[34].w[0];
+        xl.v[0][kX_S0][lane] = x.s[0].w[0];
+    } else {
+        xl.v[0][kX_S50][lane] = x.s[50].w[0];
+        xl.v[0][kX_S99][lane] = x.s[99].w[0];
+        xl.v[0][kX_S67][lane] = x.s[67].w[0];
+    }
+    lds_barrier();
+    if constexpr (ROLE == 0) {
+        in.a.w[0] = xl.v[0][kX_R99][lane];
+        in.b.w[0] = xl.v[0][kX_R67][lane];
+        in.c.w[0] = xl.v[0][kX_S34][lane];
+        in.d.w[0] = xl.v[0][kX_S0][lane];
+    } else if constexpr (ROLE == 1) {
+        x.r[49].w[0] = xl.v[0][kX_R49][lane];
+        in.a.w[0] = xl.v[0][kX_S34][lane];
+    } else if constexpr (ROLE == 2) {
+        x.s[50].w[0] = xl.v[0][kX_S50][lane];
+        in.a.w[0] = xl.v[0][kX_S99][lane];
+        in.b.w[0] = xl.v[0][kX_S67][lane];
+        in.c.w[0] = xl.v[0][kX_R33][lane];
+    } else {
+        x.s[49].w[0] = xl.v[0][kX_S49][lane];
+        in.a.w[0] = xl.v[0][kX_R33][lane];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (ROLE == 0) {
+        if (fr0) fresh[g] = 0u;  // every wave read it before the barrier
+    }
+    auto clock = [&](auto ph) {
+        constexpr int PH = decltype(ph)::value;
+        if constexpr (ROLE == 0) s4_clock_rlo<PH>(x, in, xl, lane);
+        else if constexpr (ROLE == 1) s4_clock_rhi<PH>(x, in, xl, lane);
+        else if constexpr (ROLE == 2) s4_clock_slo<PH>(x, in, xl, lane);
+        else s4_clock_shi<PH>(x, in, xl, lane);
+    };
+    char *plane = (char *)zplanes;  // wave-uniform (wave 0)
+    uint32_t blk = 0;
+    for (; blk < nblocks && active; blk++) {
+        for (int c = 0; c < 32; c += 2) {  // clock t writes exchange buffer (t + 1) & 1
+            if constexpr (ROLE == 0) {
+                store_plane<1>(plane, voff, x.r[0] ^ in.d);
+                plane += pitch;
+            }
+            clock(std::integral_constant<int, 1>{});
+            if constexpr (ROLE == 0) {
+                store_plane<1>(plane, voff, x.r[0] ^ in.d);
+                plane += pitch;
+            }
+            clock(std::integral_constant<int, 0>{});
+        }
+        if (blk + 1u == next_end) {
+            const uint32_t finished = ending_lanes(lane_left, g, active, blk, next_end);
+            for (uint32_t l = 0; l < 32; l++) {
+                if ((finished >> l) & 1u) {
+                    write_back_range<J0, J1>(x, l, pool + 25ull * lane_sid[g * 32u + l]);
+                    if constexpr (ROLE == 0) done_list[atomicAdd(done_count, 1u)] = g * 32u + l;
+                }
+            }
+            active &= ~finished;
+        }
+    }
+    lds_barrier();  // every wave has read lane_left for the last time
+    uint32_t v = voff;
+    asm volatile("" : "+v"(v));
+#pragma unroll
+    for (int j = 0; j < 50; j++) {
+        if constexpr (kR) st_word<1>((char *)planes + (size_t)(base + j0 + j) * pitch + v, x.r[j0 + j]);
+        else st_word<1>((char *)planes + (size_t)(base + j0 + j) * pitch + v, x.s[j0 + j]);
+    }
+    if constexpr (ROLE == 0) staged_advance(g, blk, lane_out, lane_left, row_dst, row_cnt);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void quantum_split4_kernel(
+    uint32_t *__restrict__ planes, uint32_t nslices, uint32_t nblocks, uint32_t **lane_out,
+    uint32_t *__restrict__ lane_left, const uint32_t *__restrict__ lane_sid, uint8_t *__restrict__ pool,
+    uint32_t *__restrict__ fresh, uint32_t *__restrict__ zplanes, uint32_t **row_dst, uint32_t *__restrict__ row_cnt,
+    uint32_t *__restrict__ done_list, uint32_t *__restrict__ done_count)
+{
+    __shared__ Split4Lds xl;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t g = blockIdx.x * 64u + lane;  // nslices is a multiple of 64
+    uint32_t next_end;
+    const uint32_t active = scan_lanes(lane_left, g, next_end);
+    if (!active) {  // all four waves leave here, before any barrier
+        if (wave == 0)
+            for (int l = 0; l < 32; l++) row_cnt[g * 32u + l] = 0u;
+        return;
+    }
+    const size_t pitch = (size_t)nslices * 4u;
+    const uint32_t voff = g * 4u;
+    const uint32_t fr0 = fresh[g];
+    if (wave == 0)
+        serve4_run<0>(planes, pitch, voff, g, lane, nblocks, active, next_end, fr0, lane_out, lane_left, lane_sid,
+                      pool, fresh, zplanes, row_dst, row_cnt, done_list, done_count, xl);
+    else if (wave == 1)
+        serve4_run<1>(planes, pitch, voff, g, lane, nblocks, active, next_end, fr0, lane_out, lane_left, lane_sid,
+                      pool, fresh, zplanes, row_dst, row_cnt, done_list, done_count, xl);
+    else if (wave == 2)
+        serve4_run<2>(planes, pitch, voff, g, lane, nblocks, active, next_end, fr0, lane_out, lane_left, lane_sid,
+                      pool, fresh, zplanes, row_dst, row_cnt, done_list, done_count, xl);
+    else
+        serve4_run<3>(planes, pitch, voff, g, lane, nblocks, active, next_end, fr0, lane_out, lane_left, lane_sid,
+                      pool, fresh, zplanes, row_dst, row_cnt, done_list, done_count, xl);
+}
+
 // Rows of the staged quantum: lane i's row_cnt[i] words of the launch go to row_dst[i],
 // tiles of 16 slices x 1024 clocks as in the plain path's staged transpose.  Tiles whose
-// lanes have no word in the tile's clocks skip the plane reads.
+// lanes have no word in the tile's clocks skip the plane reads.  The tile's 512 row
+// destinations and counts are read once, beside the plane reads, into LDS, so the stores
+// do not wait on a pointer load each.
 __global__ __launch_bounds__(256) void serve_transpose_kernel(const uint32_t *__restrict__ zplanes, uint32_t nslices,
                                                               uint32_t nclocks, uint32_t *const *row_dst,
                                                               const uint32_t *__restrict__ row_cnt)
 {
     __shared__ uint32_t lds[kTpLdsWords];
+    __shared__ uint32_t *dsts[32 * kTpSlices];
+    __shared__ uint32_t cnts[32 * kTpSlices];
     const uint32_t tid = threadIdx.x;
     const uint32_t s0 = blockIdx.x * kTpSlices;
     const uint32_t t0 = blockIdx.y * kTpClocks;
     const uint32_t w0 = t0 / 32u;
     const uint32_t nb = min((uint32_t)kTpBlocks, (nclocks - t0) / 32u);
-    const bool any = row_cnt[32u * s0 + tid] > w0 || row_cnt[32u * s0 + tid + 256u] > w0;
-    if (!__syncthreads_or(any)) return;
-    tile_to_rows(lds, zplanes, nslices, s0, t0, nb, tid);
+    const uint32_t c0 = row_cnt[32u * s0 + tid], c1 = row_cnt[32u * s0 + tid + 256u];
+    if (!__syncthreads_or(c0 > w0 || c1 > w0)) return;
+    uint32_t *const d0 = row_dst[32u * s0 + tid], *const d1 = row_dst[32u * s0 + tid + 256u];
+    tile_to_rows(lds, zplanes, nslices, s0, t0, nb, tid, [&] {
+        cnts[tid] = c0;
+        cnts[tid + 256u] = c1;
+        dsts[tid] = d0;
+        dsts[tid + 256u] = d1;
+    });
     const uint32_t w = tid & 31u;
+    if (w >= nb) return;
     for (uint32_t i = tid >> 5; i < 32u * kTpSlices; i += 8u) {
-        const uint32_t lane = 32u * s0 + i;
-        const uint32_t cnt = row_cnt[lane];
-        if (w0 + w < cnt && w < nb) store_global(row_dst[lane] + w0 + w, tile_row_word(lds, i, w));
+        if (w0 + w < cnts[i]) store_global(dsts[i] + w0 + w, tile_row_word(lds, i, w));
     }
 }
 
@@ -733,6 +904,13 @@ __global__ __launch_bounds__(256) void serve_transpose_kernel(const uint32_t *__
 __global__ void reset_count_kernel(uint32_t *c)
 {
     if (threadIdx.x == 0) *c = 0u;
+}
+
+// Copy the completion counter to the host's mapped word (a system-scope store, seen by the
+// host once the event after this kernel has completed).
+__global__ void publish_count_kernel(const uint32_t *c, uint32_t *host)
+{
+    if (threadIdx.x == 0) __hip_atomic_store(host, *c, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // The request owning state sid is done: the next request waiting on it (if any) becomes
@@ -779,6 +957,8 @@ int retire_oldest(mickey_server *s)
     const uint64_t t1 = now_ns();
     s->ns_wait += t1 - tw;
     s->quanta_ns += t1 - s->launch_ns[b];
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->ev_start[b], s->ev[b]) == hipSuccess) s->ns_gpu += (uint64_t)(ms * 1e6f);
     const uint32_t ndone = s->hcount[b];
     const uint32_t *list = s->hlist + (size_t)b * (s->nlanes + kLatStreams);
     for (uint32_t k = 0; k < ndone; k++) {
@@ -969,7 +1149,6 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
                hipMalloc(&s->fresh, s->nslices * 4) == hipSuccess &&
                hipMalloc(&s->sink, s->nslices * 4) == hipSuccess &&
                hipMalloc(&s->done_list, 256) == hipSuccess &&
-               hipMalloc(&s->dadm, (s->nlanes + kLatStreams) * sizeof(Admit)) == hipSuccess &&
                hipMalloc(&s->lat_state, kLatStreams * 8 * 4) == hipSuccess &&
                hipMalloc(&s->lat_out, kLatStreams * sizeof(uint32_t *)) == hipSuccess &&
                hipMalloc(&s->lat_left, kLatStreams * 4) == hipSuccess &&
@@ -979,13 +1158,19 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
                hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) == hipSuccess &&
                hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) == hipSuccess &&
                hipMalloc(&s->arena, budget_words * 4) == hipSuccess &&
-               hipHostMalloc((void **)&s->hadm, (s->nlanes + kLatStreams) * sizeof(Admit), hipHostMallocDefault) ==
-                   hipSuccess &&
-               hipHostMalloc((void **)&s->hcount, 64, hipHostMallocDefault) == hipSuccess &&
+               hipHostMalloc((void **)&s->hadm_buf[0], (s->nlanes + kLatStreams) * sizeof(Admit),
+                             hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+               hipHostGetDevicePointer((void **)&s->hadm_dev[0], s->hadm_buf[0], 0) == hipSuccess &&
+               hipHostMalloc((void **)&s->hadm_buf[1], (s->nlanes + kLatStreams) * sizeof(Admit),
+                             hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+               hipHostGetDevicePointer((void **)&s->hadm_dev[1], s->hadm_buf[1], 0) == hipSuccess &&
+               hipHostMalloc((void **)&s->hcount, 64, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+               hipHostGetDevicePointer((void **)&s->hcount_dev, s->hcount, 0) == hipSuccess &&
                hipHostMalloc((void **)&s->hlist, 2 * (s->nlanes + kLatStreams) * 4, hipHostMallocMapped) == hipSuccess &&
                hipHostGetDevicePointer((void **)&s->hlist_dev, s->hlist, 0) == hipSuccess &&
-               hipEventCreateWithFlags(&s->ev[0], hipEventDisableTiming) == hipSuccess &&
-               hipEventCreateWithFlags(&s->ev[1], hipEventDisableTiming) == hipSuccess;
+               hipEventCreate(&s->ev[0]) == hipSuccess && hipEventCreate(&s->ev[1]) == hipSuccess &&
+               hipEventCreate(&s->ev_start[0]) == hipSuccess && hipEventCreate(&s->ev_start[1]) == hipSuccess;
+    s->hadm = s->hadm_buf[0];
     if (!okm) {
         (void)hipGetLastError();
         destroy(s);
@@ -1067,11 +1252,17 @@ int launch_quantum(mickey_server *s, int b)
                            s->fresh, s->sink, list, s->done_count + b);
         return check_launch("quantum_kernel");
     }
-    const bool split = s->schedule == MICKEY_SCHED_SPLIT ||
-                       (s->schedule == MICKEY_SCHED_AUTO && s->nslices / 64 <= (size_t)s->simds);
+    // the plain path's rule: the four-wave split below two one-wave waves per SIMD
+    const bool split4 = s->schedule == MICKEY_SCHED_SPLIT4 ||
+                        (s->schedule == MICKEY_SCHED_AUTO && s->nslices / 64 < 2 * (size_t)s->simds);
+    const bool split = s->schedule == MICKEY_SCHED_SPLIT;
     for (uint32_t b0 = 0; b0 < s->qblocks; b0 += s->sub_blocks) {
         const uint32_t nb = std::min(s->sub_blocks, s->qblocks - b0);
-        if (split)
+        if (split4)
+            hipLaunchKernelGGL(quantum_split4_kernel, dim3((unsigned)(s->nslices / 64)), dim3(256), 0, s->stream,
+                               s->planes, (uint32_t)s->nslices, nb, s->lane_out, s->lane_left, s->lane_sid, s->pool,
+                               s->fresh, s->zplanes, s->row_dst, s->row_cnt, list, s->done_count + b);
+        else if (split)
             hipLaunchKernelGGL(quantum_split_kernel, dim3((unsigned)(s->nslices / 64)), dim3(128), 0, s->stream,
                                s->planes, (uint32_t)s->nslices, nb, s->lane_out, s->lane_left, s->lane_sid, s->pool,
                                s->fresh, s->zplanes, s->row_dst, s->row_cnt, list, s->done_count + b);
@@ -1097,10 +1288,13 @@ int mickey_server_step(mickey_server *s)
     if (s->oldest_q == s->next_q) decide_admissions(s);  // idle: admit before launching
     // 1. gather the admissions decided last time (stream-ordered after the quanta in flight)
     if (s->pending) {
-        if (hipMemcpyAsync(s->dadm, s->hadm, s->pending * sizeof(Admit), hipMemcpyHostToDevice, s->stream) !=
-            hipSuccess)
-            return check_launch("admission upload");
-        hipLaunchKernelGGL(admit_kernel, dim3((s->pending + 255) / 256), dim3(256), 0, s->stream, s->dadm,
+        // the kernel reads this buffer when the stream reaches it, after the quantum in
+        // flight, which the host does not wait for before deciding the next admissions: they
+        // go to the other buffer, whose reader preceded that quantum
+        const Admit *adm = s->hadm_dev[s->adm_b];
+        s->adm_b ^= 1;
+        s->hadm = s->hadm_buf[s->adm_b];
+        hipLaunchKernelGGL(admit_kernel, dim3((s->pending + 255) / 256), dim3(256), 0, s->stream, adm,
                            s->pending, (uint32_t)s->nlanes, s->lane_out, s->lane_left, s->lane_sid, s->fresh,
                            s->lat_out, s->lat_left, s->lat_sid, s->lat_fresh);
         rc = check_launch("admit_kernel");
@@ -1113,6 +1307,7 @@ int mickey_server_step(mickey_server *s)
     const bool any_bs = s->free_lanes.size() < s->nlanes, any_lat = s->lat_busy > 0;
     if (any_bs || any_lat) {
         const int b = (int)(s->next_q & 1);
+        if (hipEventRecord(s->ev_start[b], s->stream) != hipSuccess) return check_launch("quantum start");
         hipLaunchKernelGGL(reset_count_kernel, dim3(1), dim3(64), 0, s->stream, s->done_count + b);
         s->launch_ns[b] = now_ns();
         if (any_lat) {
@@ -1133,9 +1328,8 @@ int mickey_server_step(mickey_server *s)
             if (rc != MICKEY_OK) return rc;
         }
         if (any_lat && hipStreamWaitEvent(s->stream, s->ev_join, 0) != hipSuccess) return check_launch("latency join");
-        if (hipMemcpyAsync(s->hcount + b, s->done_count + b, 4, hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
-            hipEventRecord(s->ev[b], s->stream) != hipSuccess)
-            return check_launch("completion count");
+        hipLaunchKernelGGL(publish_count_kernel, dim3(1), dim3(64), 0, s->stream, s->done_count + b, s->hcount_dev + b);
+        if (hipEventRecord(s->ev[b], s->stream) != hipSuccess) return check_launch("completion count");
         s->next_q++;
         s->steps++;
     }
@@ -1252,8 +1446,8 @@ int mickey_server_release(mickey_server *s, uint64_t id)
 // [2] admitted, [3] finished, [4] steps,
 // [5] total quantum time (ns, launch to retirement), [6] keystream bits delivered,
 // [7] free budget words, [8] host ns blocked on quanta, [9] host ns retiring,
-// [10] host ns deciding admissions.
-int mickey_server_stats(const mickey_server *s, uint64_t out[11])
+// [10] host ns deciding admissions, [11] device ns of the quanta.
+int mickey_server_stats(const mickey_server *s, uint64_t out[12])
 {
     if (!s || !out) return fail(MICKEY_EINVAL, "mickey_server_stats: bad argument");
     const size_t freew = s->alloc.free_words() + s->slice_cached;
@@ -1268,6 +1462,7 @@ int mickey_server_stats(const mickey_server *s, uint64_t out[11])
     out[8] = s->ns_wait;
     out[9] = s->ns_retire;
     out[10] = s->ns_admit;
+    out[11] = s->ns_gpu;
     return ok();
 }
 
@@ -1311,14 +1506,16 @@ int mickey_server_set_latency(mickey_server *s, uint32_t streams, uint64_t thres
 int mickey_server_set_kernel(mickey_server *s, int schedule, int transpose)
 {
     if (!s) return fail(MICKEY_EINVAL, "mickey_server_set_kernel: NULL server");
-    if (schedule != MICKEY_SCHED_AUTO && schedule != MICKEY_SCHED_ONE_WAVE && schedule != MICKEY_SCHED_SPLIT)
+    if (schedule != MICKEY_SCHED_AUTO && schedule != MICKEY_SCHED_ONE_WAVE && schedule != MICKEY_SCHED_SPLIT &&
+        schedule != MICKEY_SCHED_SPLIT4)
         return fail(MICKEY_EINVAL, "mickey_server_set_kernel: unknown schedule %d", schedule);
     if (transpose != MICKEY_TRANSPOSE_AUTO && transpose != MICKEY_TRANSPOSE_FUSED &&
         transpose != MICKEY_TRANSPOSE_STAGED)
         return fail(MICKEY_EINVAL, "mickey_server_set_kernel: unknown transpose mode %d", transpose);
-    if (transpose == MICKEY_TRANSPOSE_FUSED && schedule == MICKEY_SCHED_SPLIT)
+    const bool any_split = schedule == MICKEY_SCHED_SPLIT || schedule == MICKEY_SCHED_SPLIT4;
+    if (transpose == MICKEY_TRANSPOSE_FUSED && any_split)
         return fail(MICKEY_EINVAL, "mickey_server_set_kernel: the fused kernel runs the one-wave schedule");
-    if (!s->sub_blocks && (transpose == MICKEY_TRANSPOSE_STAGED || schedule == MICKEY_SCHED_SPLIT))
+    if (!s->sub_blocks && (transpose == MICKEY_TRANSPOSE_STAGED || any_split))
         return fail(MICKEY_EINVAL, "mickey_server_set_kernel: staging needs one 32-clock plane chunk per "
                                    "launch within 512 MiB (too many slots)");
     s->schedule = schedule;

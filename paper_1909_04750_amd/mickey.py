@@ -435,7 +435,7 @@ class Server:
     """mickey_server: resident states, resumable requests, continuous batching."""
 
     STAT_KEYS = ("waiting", "running", "admitted", "finished", "steps", "quantum_ns", "bits_delivered",
-                 "free_budget_words", "host_wait_ns", "host_retire_ns", "host_admit_ns")
+                 "free_budget_words", "host_wait_ns", "host_retire_ns", "host_admit_ns", "gpu_ns")
 
     def __init__(self, init: "Mickey", nslices: int, quantum_clocks: int, budget_bytes: int, stream=None):
         L = load_library()
@@ -541,7 +541,7 @@ class Server:
         _check(load_library().mickey_server_release(self._h, int(rid)))
 
     def stats(self) -> dict:
-        out = (ctypes.c_uint64 * 11)()
+        out = (ctypes.c_uint64 * len(self.STAT_KEYS))()
         _check(load_library().mickey_server_stats(self._h, out))
         return dict(zip(self.STAT_KEYS, [int(v) for v in out]))
 

@@ -29,8 +29,8 @@ def make_pool(seed, n, mixed=True):
 # (schedule, transpose) of the quantum kernels: the fused one-wave kernel, and the staged
 # kernels (bit-planes, then a tiled transpose into the requests) with each schedule
 KERNELS = [(mickey.SCHED_ONE_WAVE, mickey.TRANSPOSE_FUSED), (mickey.SCHED_ONE_WAVE, mickey.TRANSPOSE_STAGED),
-           (mickey.SCHED_SPLIT, mickey.TRANSPOSE_STAGED)]
-KERNEL_IDS = ["fused", "staged-one-wave", "staged-split"]
+           (mickey.SCHED_SPLIT, mickey.TRANSPOSE_STAGED), (mickey.SCHED_SPLIT4, mickey.TRANSPOSE_STAGED)]
+KERNEL_IDS = ["fused", "staged-one-wave", "staged-split", "staged-split4"]
 
 
 def server(init, kernel, **kw):
@@ -267,7 +267,7 @@ def test_chunked_delivery_errors():
     srv.close()
 
 
-@pytest.mark.parametrize("schedule", [mickey.SCHED_ONE_WAVE, mickey.SCHED_SPLIT])
+@pytest.mark.parametrize("schedule", [mickey.SCHED_ONE_WAVE, mickey.SCHED_SPLIT, mickey.SCHED_SPLIT4])
 def test_staged_quantum_in_several_launches(schedule):
     """2^17 slices: one 1024-clock launch of planes fills the 512 MiB staging buffer, so a
     quantum of 2144 clocks runs as launches of 1024, 1024 and 96 clocks; requests that end
@@ -292,8 +292,8 @@ def test_set_kernel_errors():
     keys, ivs, ivb, init = make_pool(12, 8, mixed=False)
     srv = mickey.Server(init, nslices=64, quantum_clocks=32, budget_bytes=1 << 12)
     init.close()
-    for sched, tp in ((3, mickey.TRANSPOSE_AUTO), (mickey.SCHED_AUTO, 3),
-                      (mickey.SCHED_SPLIT, mickey.TRANSPOSE_FUSED)):
+    for sched, tp in ((4, mickey.TRANSPOSE_AUTO), (mickey.SCHED_AUTO, 3),
+                      (mickey.SCHED_SPLIT, mickey.TRANSPOSE_FUSED), (mickey.SCHED_SPLIT4, mickey.TRANSPOSE_FUSED)):
         with pytest.raises(mickey.MickeyError) as e:
             srv.set_kernel(sched, tp)
         assert e.value.code == mickey.EINVAL
