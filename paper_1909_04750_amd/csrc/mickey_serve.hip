@@ -961,7 +961,17 @@ int retire_oldest(mickey_server *s)
     if (hipEventElapsedTime(&ms, s->ev_start[b], s->ev[b]) == hipSuccess) s->ns_gpu += (uint64_t)(ms * 1e6f);
     const uint32_t ndone = s->hcount[b];
     const uint32_t *list = s->hlist + (size_t)b * (s->nlanes + kLatStreams);
+    // the loop's reads are spread over tables of 10^6 entries (lane -> request -> state), so
+    // it fetches each level a few completions ahead instead of waiting on every miss
+    constexpr uint32_t kAhead = 8;
     for (uint32_t k = 0; k < ndone; k++) {
+        if (k + 3 * kAhead < ndone) __builtin_prefetch(&s->lane_req[list[k + 3 * kAhead]]);
+        if (k + 2 * kAhead < ndone) {
+            const char *q = (const char *)&s->reqs[s->lane_req[list[k + 2 * kAhead]]];
+            __builtin_prefetch(q, 1);
+            __builtin_prefetch(q + 64, 1);
+        }
+        if (k + kAhead < ndone) __builtin_prefetch(&s->state_bits[s->reqs[s->lane_req[list[k + kAhead]]].sid], 1);
         const uint32_t lane = list[k];
         Request &r = s->reqs[s->lane_req[lane]];
         s->lane_req[lane] = ~0ull;
@@ -1063,7 +1073,23 @@ void decide_admissions(mickey_server *s)
 {
     const uint64_t t_admit = now_ns();
     bool full = false;
+    constexpr size_t kAhead = 8;
     while (!s->continuing.empty()) {
+        // prefetch a few admissions ahead: the request, and the block cache of the lane it
+        // will take (the free lanes are taken from the back)
+        if (s->continuing.size() > kAhead) {
+            const char *q = (const char *)&s->reqs[s->continuing[kAhead]];
+            __builtin_prefetch(q, 1);
+            __builtin_prefetch(q + 64, 1);
+        }
+        const size_t nf = s->free_lanes.size();
+        if (nf > 2 * kAhead) __builtin_prefetch(&s->slice_blocks[cache_index(s, s->free_lanes[nf - 1 - 2 * kAhead])]);
+        if (nf > kAhead) {
+            const uint32_t l = s->free_lanes[nf - 1 - kAhead];
+            const auto &c = s->slice_blocks[cache_index(s, l)];
+            if (!c.empty()) __builtin_prefetch(&c.back());
+            __builtin_prefetch(&s->lane_req[l], 1);
+        }
         if (!admit_next(s, s->reqs[s->continuing.front()], t_admit)) {
             full = true;
             break;
@@ -1546,7 +1572,15 @@ int mickey_server_release_chunks(mickey_server *s, const uint64_t *handles, size
 {
     if (!s || (n && !handles)) return fail(MICKEY_EINVAL, "mickey_server_release_chunks: bad argument");
     int first = MICKEY_OK;
+    constexpr size_t kAhead = 8;
     for (size_t k = 0; k < n; k++) {
+        if (k + 2 * kAhead < n && handles[k + 2 * kAhead] < s->slots.size())
+            __builtin_prefetch(&s->slots[handles[k + 2 * kAhead]], 1);
+        if (k + kAhead < n && handles[k + kAhead] < s->slots.size()) {
+            const auto &c = s->slice_blocks[s->slots[handles[k + kAhead]].slice];
+            __builtin_prefetch(&c);
+            __builtin_prefetch(c.data() + c.size(), 1);
+        }
         const uint64_t h = handles[k];
         if (h >= s->slots.size() || !s->slots[h].live) {
             if (first == MICKEY_OK)
