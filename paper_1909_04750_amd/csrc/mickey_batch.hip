@@ -131,13 +131,8 @@ __global__ __launch_bounds__(64) void latency_kernel(const uint8_t *__restrict__
     uint32_t *out = lane_out[i];
     const uint32_t nw = lane_words[i];
     for (uint32_t j = 0; j < nw; j++) {
-        uint32_t acc = 0;
-#pragma unroll
-        for (int b = 0; b < 32; b++) {
-            acc = __builtin_amdgcn_alignbit(r ^ s, acc, 1);  // z = r_0 ^ s_0 (lane 0) enters at bit 31
-            quad_clock(r, s, m);
-        }
-        if (q == 0) store_global(out + j, __builtin_bitreverse32(acc));  // first bit of the word in the MSB
+        const uint32_t word = quad_word(r, s, m);
+        if (q == 0) store_global(out + j, word);
     }
 }
 

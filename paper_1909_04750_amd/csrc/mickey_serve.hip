@@ -350,13 +350,8 @@ __global__ __launch_bounds__(64) void latency_quantum_kernel(uint32_t *__restric
     uint32_t *out = lat_out[k];
     const uint32_t nw = left < nwords ? left : nwords;
     for (uint32_t w = 0; w < nw; w++) {
-        uint32_t acc = 0;
-#pragma unroll
-        for (int b = 0; b < 32; b++) {
-            acc = __builtin_amdgcn_alignbit(r ^ s, acc, 1);  // z = r_0 ^ s_0 (lane 0) enters at bit 31
-            quad_clock(r, s, m);
-        }
-        if (q == 0) store_global(out + w, __builtin_bitreverse32(acc));  // first bit in the MSB
+        const uint32_t word = quad_word(r, s, m);
+        if (q == 0) store_global(out + w, word);
     }
     if (nw == left) {
         quad_write_back(r, s, q, pool + 25ull * lat_sid[k]);

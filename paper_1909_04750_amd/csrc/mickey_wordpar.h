@@ -95,21 +95,26 @@ __device__ __forceinline__ void wclock(WState &x, uint32_t in_m)
 // Per clock the quad XOR-reduces each lane's share of the four bits that steer the clock
 // (s_34 ^ r_67 = c_R, r_33 ^ s_67 = c_S, r_99 = fb_R, s_99 = fb_S) with two DPP swaps,
 // fetches its neighbours' words for the shifts with DPP quad permutes, and updates its two
-// words: ~29 VALU per clock instead of ~52, i.e. about twice as fast for one instance (one
+// words: ~25 VALU per clock instead of ~52, i.e. about twice as fast for one instance (one
 // wave issues at most ~0.4 instructions/ns, so the count per clock sets the speed).
+// The shift up takes word q-1 from lane q-1 and, in lane 0, word 3 by a rotating permute:
+// bits 100..127 of word 3 are kept zero often enough that the bit it shifts into r_0 and
+// s_0 (bit 127) is always zero.  Those bits only ever take bit 99 shifted upwards (no tap,
+// comparison or feedback position lies above 99), one position per clock, so clearing them
+// every 16 clocks keeps bits 116..127 zero; quad_word does that.
 // Every lane of a quad must be active.
 
 constexpr int qp(int a, int b, int c, int d) { return a | (b << 2) | (c << 4) | (d << 6); }
 template <int CTRL>
 __device__ __forceinline__ uint32_t qperm(uint32_t v)
 {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
 }
 __device__ __forceinline__ uint32_t bitmask_i(uint32_t v, int b) { return (uint32_t)((int32_t)(v << (31 - b)) >> 31); }
 
 struct QuadMasks {
     uint32_t taps, comp0, comp1, fb0, fb1, inner;  // word q of the position masks
-    uint32_t prev;                                 // 0 in lane 0: nothing shifts into r_0, s_0
+    uint32_t keep;                                 // lane 3: bits 96..99 only
     uint32_t ra, rm, sa, sm;                       // this lane's share of the steering bits
 };
 
@@ -127,7 +132,7 @@ __device__ __forceinline__ QuadMasks quad_masks(uint32_t q)
     m.fb0 = pick4(q, kWM.fb0[0], kWM.fb0[1], kWM.fb0[2], kWM.fb0[3]);
     m.fb1 = pick4(q, kWM.fb1[0], kWM.fb1[1], kWM.fb1[2], kWM.fb1[3]);
     m.inner = pick4(q, kWM.inner[0], kWM.inner[1], kWM.inner[2], kWM.inner[3]);
-    m.prev = q ? 0xFFFFFFFFu : 0u;
+    m.keep = q == 3 ? 0xFu : 0xFFFFFFFFu;
     // v bit 0: c_R (s_34 in lane 1, r_67 in lane 2), bit 1: c_S (r_33 in lane 1, s_67 in
     // lane 2), bit 2: fb_R (r_99, lane 3), bit 3: fb_S (s_99, lane 3)
     m.ra = pick4(q, 0, 0, 3, 1);
@@ -137,14 +142,15 @@ __device__ __forceinline__ QuadMasks quad_masks(uint32_t q)
     return m;
 }
 
+// One clock; bit 127 of r and s (word 3, bit 31) must be zero (see quad_word).
 __device__ __forceinline__ void quad_clock(uint32_t &r, uint32_t &s, const QuadMasks &m)
 {
     uint32_t v = ((r >> m.ra) & m.rm) ^ ((s >> m.sa) & m.sm);
     v ^= qperm<qp(1, 0, 3, 2)>(v);
     v ^= qperm<qp(2, 3, 0, 1)>(v);
     const uint32_t cr = bitmask_i(v, 0), cs = bitmask_i(v, 1), fbr = bitmask_i(v, 2), fbs = bitmask_i(v, 3);
-    const uint32_t rp = qperm<qp(0, 0, 1, 2)>(r) & m.prev;
-    const uint32_t sp = qperm<qp(0, 0, 1, 2)>(s) & m.prev;
+    const uint32_t rp = qperm<qp(3, 0, 1, 2)>(r);  // lane 0: word 3, whose bit 31 is zero
+    const uint32_t sp = qperm<qp(3, 0, 1, 2)>(s);
     const uint32_t sn = qperm<qp(1, 2, 3, 3)>(s);
     const uint32_t rl = __builtin_amdgcn_alignbit(r, rp, 31);  // register shifted up by one
     const uint32_t sl = __builtin_amdgcn_alignbit(s, sp, 31);
@@ -156,6 +162,23 @@ __device__ __forceinline__ void quad_clock(uint32_t &r, uint32_t &s, const QuadM
     const uint32_t h = __builtin_amdgcn_bitop3_b32(sl, qv, y, TA ^ (TB & TC));
     const uint32_t fsel = __builtin_amdgcn_bitop3_b32(cs, m.fb1, m.fb0, (TA & TB) | (~TA & TC));
     s = __builtin_amdgcn_bitop3_b32(h, fbs, fsel, TA ^ (TB & TC));
+}
+
+// 32 clocks; returns their keystream bits, the first in the MSB (valid in lane 0).  Clears
+// bits 100..127 before clocks 0 and 16, so any value of them on entry is allowed.
+__device__ __forceinline__ uint32_t quad_word(uint32_t &r, uint32_t &s, const QuadMasks &m)
+{
+    uint32_t acc = 0;
+#pragma unroll
+    for (int b = 0; b < 32; b++) {
+        if (b % 16 == 0) {
+            r &= m.keep;
+            s &= m.keep;
+        }
+        acc = __builtin_amdgcn_alignbit(r ^ s, acc, 1);  // z = r_0 ^ s_0 (lane 0) enters at bit 31
+        quad_clock(r, s, m);
+    }
+    return __builtin_bitreverse32(acc);
 }
 
 }  // namespace mickey
