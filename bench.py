@@ -297,8 +297,9 @@ def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 
                                   "batch_speedup": round(serial_ms / batch_ms, 1)}}
 
 
-def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: float, lat_ratio: int = 8,
-                lat_streams: int = 16384, lat_threshold: int = 1 << 20, rate: float = 20000.0,
+def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: float, qclocks: int = 8192,
+                lat_ratio: int = 4,
+                lat_streams: int = 16384, lat_threshold: int = 1 << 26, rate: float = 20000.0,
                 nstates: int = 10 ** 6, budget: int = 64 << 30, chunk: int = 64 << 10, sat_seconds: float = 3.0,
                 nverify: int = 16):
     """Served generation over 10^6 resident states (splitmix64 seed 5 keys and 80-bit
@@ -323,7 +324,7 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
     cand = first[nbits[first] <= 8 * (256 << 10)]
     verify = set(np.sort(cand)[:: max(1, len(cand) // nverify)][:nverify].tolist())
     vwords = {k: [] for k in verify}
-    nslices, qclocks = 32768, 2048
+    nslices = 32768
     srv = mickey.Server(init, nslices=nslices, quantum_clocks=qclocks, budget_bytes=budget)
     srv.set_chunk(chunk)
     # size-aware routing: what is left of a request of lat_threshold bits or more takes one
@@ -537,10 +538,11 @@ def main() -> int:
     ap.add_argument("--serve-max-kib", type=int, default=64 << 10, help="largest served request (KiB)")
     ap.add_argument("--serve-drain", type=float, default=90.0,
                     help="seconds the open-loop served run continues after the last arrival")
-    ap.add_argument("--serve-lat-ratio", type=int, default=8,
+    ap.add_argument("--serve-quantum", type=int, default=8192, help="open loop: clocks per quantum (multiple of 32)")
+    ap.add_argument("--serve-lat-ratio", type=int, default=4,
                     help="open loop: latency-stream clocks per quantum, as a multiple of the quantum")
     ap.add_argument("--serve-lat-streams", type=int, default=16384, help="open loop: latency streams (0: off)")
-    ap.add_argument("--serve-lat-kib", type=int, default=128,
+    ap.add_argument("--serve-lat-kib", type=int, default=8192,
                     help="open loop: requests with at least this many KiB left take latency streams")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
@@ -688,7 +690,7 @@ def main() -> int:
         res["batch_10k"] = bench_batch(torch, mickey, synth)
     if not args.no_serve:
         res["serve"] = bench_serve(torch, mickey, synth, args.serve_seconds, args.serve_max_kib << 10,
-                                   args.serve_drain, args.serve_lat_ratio, args.serve_lat_streams,
+                                   args.serve_drain, args.serve_quantum, args.serve_lat_ratio, args.serve_lat_streams,
                                    args.serve_lat_kib << 13)
     print(json.dumps(res), flush=True)
     return 0
