@@ -528,7 +528,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-word64", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=131072,
+                    help="instances the oracle runs for cpu_baseline (~10-15 s on 16 host threads)")
     ap.add_argument("--no-rowmajor", action="store_true", help="skip the row-major 2^20 x 65536 measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 10,000-request batched measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the served measurements")

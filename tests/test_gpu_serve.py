@@ -144,6 +144,9 @@ def test_budget_admission_and_overlap():
     assert a_later < srv.times(long)[2]  # admitted before `long` finished: they overlapped
     want = oracle_history(keys, ivs, None, 52, [64])[0]
     assert (fetch(srv, later, 64) == want).all()
+    # device time of the quanta: positive, and within the launch-to-retirement time
+    st = srv.stats()
+    assert 0 < st["gpu_ns"] <= st["quantum_ns"]
     srv.close()
 
 
