@@ -93,15 +93,14 @@ __device__ __forceinline__ Next step(const State &x)
     const uint32_t m = x0 ^ x4;
     const uint32_t mj = op3<kMaj>(x0, x1, x4);
     const uint32_t bb = op3<kB>(x3, m, mj);
-    uint32_t a = op3<kXor3>(GB(1), GB(2), GB(4));
-    a = op3<kXor3>(a, GB(10), GB(31));
-    a = op3<kXor3>(a, GB(43), GB(56));
-    a = op3<kXor3>(a, x1, f);
+    // the sums are balanced trees of three-input XORs: one clock's work is a few short
+    // chains rather than one long one, which two waves per SIMD could not hide
+    const uint32_t a = op3<kXor3>(op3<kXor3>(GB(1), GB(2), GB(4)), op3<kXor3>(GB(10), GB(31), GB(43)),
+                                  op3<kXor3>(GB(56), x1, f));
     const uint32_t z = op3<kXorAnd>(a, x2, bb);
     // s_{t+80}
-    uint32_t fs = op3<kXor3>(GS(0), GS(13), GS(23));
-    fs = op3<kXor3>(fs, GS(38), GS(51));
-    fs = INIT ? op3<kXor3>(fs, GS(62), z) : (fs ^ GS(62));
+    const uint32_t f1 = op3<kXor3>(GS(0), GS(13), GS(23)), f2 = op3<kXor3>(GS(38), GS(51), GS(62));
+    const uint32_t fs = INIT ? op3<kXor3>(f1, f2, z) : (f1 ^ f2);
     // b_{t+80} = s_t ^ g(b): pair products shared by several monomials
     const uint32_t p1 = GB(63) & GB(60), p2 = GB(37) & GB(33), p3 = GB(15) & GB(9);
     const uint32_t p4 = GB(52) & GB(45), p5 = GB(28) & GB(21);
@@ -111,19 +110,15 @@ __device__ __forceinline__ Next step(const State &x)
     const uint32_t m8 = op3<kAnd3>(p1, GB(21), GB(15));    // b63 b60 b21 b15
     const uint32_t m9 = op3<kAnd3>(p1, p4, GB(37));        // b63 b60 b52 b45 b37
     const uint32_t m11 = op3<kAnd3>(p4, p2, p5);           // b52 b45 b37 b33 b28 b21
-    uint32_t g = op3<kXor3>(GS(0), GB(62), GB(60));
-    g = op3<kXor3>(g, GB(52), GB(45));
-    g = op3<kXor3>(g, GB(37), GB(33));
-    g = op3<kXor3>(g, GB(28), GB(21));
-    g = op3<kXor3>(g, GB(14), GB(9));
-    g = op3<kXor3>(g, GB(0), p1);                          // b63 b60
-    g = op3<kXor3>(g, p2, p3);                             // b37 b33, b15 b9
-    g = op3<kXor3>(g, m5, m7);
-    g = op3<kXor3>(g, m8, m9);
-    g = INIT ? op3<kXor3>(g, m11, z) : (g ^ m11);
-    g = op3<kXorAnd>(g, GB(60), p4);                       // b60 b52 b45
-    g = op3<kXorAnd>(g, t6, GB(9));                        // b63 b45 b28 b9
-    g = op3<kXorAnd>(g, m5, p3);                           // b33 b28 b21 b15 b9
+    const uint32_t g1 = op3<kXor3>(GS(0), GB(62), GB(60)), g2 = op3<kXor3>(GB(52), GB(45), GB(37));
+    const uint32_t g3 = op3<kXor3>(GB(33), GB(28), GB(21)), g4 = op3<kXor3>(GB(14), GB(9), GB(0));
+    const uint32_t g5 = op3<kXor3>(p1, p2, p3);             // b63 b60, b37 b33, b15 b9
+    const uint32_t g6 = op3<kXor3>(m5, m7, m8);
+    const uint32_t g7 = INIT ? op3<kXor3>(m9, m11, z) : (m9 ^ m11);
+    const uint32_t q1 = op3<kXorAnd>(op3<kXor3>(g1, g2, g3), GB(60), p4);  // b60 b52 b45
+    const uint32_t q2 = op3<kXorAnd>(op3<kXor3>(g4, g5, g6), t6, GB(9));   // b63 b45 b28 b9
+    const uint32_t q3 = op3<kXorAnd>(g7, m5, p3);                          // b33 b28 b21 b15 b9
+    const uint32_t g = op3<kXor3>(q1, q2, q3);
 #undef GB
 #undef GS
     return Next{z, fs, g};
