@@ -530,6 +530,25 @@ __device__ __forceinline__ void tile_to_rows(uint32_t *lds, const uint32_t *__re
     __syncthreads();
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin by linear id, and each XCD has its own
+// L2.  xcd_grouped(lin, n) is a permutation of 0..n-1 that gives each XCD a contiguous run
+// of logical indices, so neighbouring transpose tiles, which read the two halves of the
+// same 128 B lines (16 slices are 64 B of a plane), run on one XCD and fetch each line once.
+__device__ __forceinline__ uint32_t xcd_grouped(uint32_t lin, uint32_t n)
+{
+    constexpr uint32_t kXcds = 8;
+    const uint32_t q = n / kXcds, r = n % kXcds, x = lin % kXcds;
+    return x * q + (x < r ? x : r) + lin / kXcds;
+}
+
+// (tile, clock block) of this workgroup of a transpose grid, XCD-grouped.
+__device__ __forceinline__ uint2 tile_of_block()
+{
+    const uint32_t gx = gridDim.x;
+    const uint32_t l = xcd_grouped(blockIdx.x + blockIdx.y * gx, gx * gridDim.y);
+    return make_uint2(l % gx, l / gx);
+}
+
 __device__ __forceinline__ uint32_t tile_row_word(const uint32_t *lds, uint32_t i, uint32_t q)
 {
     return lds[i * 32u + (q ^ (i >> 5))];

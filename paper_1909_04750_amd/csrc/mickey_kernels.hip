@@ -345,8 +345,9 @@ __global__ __launch_bounds__(256) void rowmajor_transpose_kernel(const uint32_t 
 {
     __shared__ uint32_t lds[kTpLdsWords];
     const uint32_t tid = threadIdx.x;
-    const uint32_t s0 = blockIdx.x * kTpSlices;
-    const uint32_t t0 = blockIdx.y * kTpClocks;
+    const uint2 tb = tile_of_block();
+    const uint32_t s0 = tb.x * kTpSlices;
+    const uint32_t t0 = tb.y * kTpClocks;
     const uint32_t nb = min((uint32_t)kTpBlocks, (nclocks - t0) / 32u);  // blocks in this tile
     tile_to_rows(lds, planes, nslices, s0, t0, nb, tid, [] {});
     const uint32_t w = tid & 31u;

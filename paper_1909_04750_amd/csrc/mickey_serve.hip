@@ -875,8 +875,9 @@ __global__ __launch_bounds__(256) void serve_transpose_kernel(const uint32_t *__
     __shared__ uint32_t *dsts[32 * kTpSlices];
     __shared__ uint32_t cnts[32 * kTpSlices];
     const uint32_t tid = threadIdx.x;
-    const uint32_t s0 = blockIdx.x * kTpSlices;
-    const uint32_t t0 = blockIdx.y * kTpClocks;
+    const uint2 tb = tile_of_block();
+    const uint32_t s0 = tb.x * kTpSlices;
+    const uint32_t t0 = tb.y * kTpClocks;
     const uint32_t w0 = t0 / 32u;
     const uint32_t nb = min((uint32_t)kTpBlocks, (nclocks - t0) / 32u);
     const uint32_t c0 = row_cnt[32u * s0 + tid], c1 = row_cnt[32u * s0 + tid + 256u];
