@@ -1331,6 +1331,8 @@ int mickey_server_step(mickey_server *s)
         const int b = (int)(s->next_q & 1);
         if (hipEventRecord(s->ev_start[b], s->stream) != hipSuccess) return check_launch("quantum start");
         hipLaunchKernelGGL(reset_count_kernel, dim3(1), dim3(64), 0, s->stream, s->done_count + b);
+        rc = check_launch("reset_count_kernel");
+        if (rc != MICKEY_OK) return rc;
         s->launch_ns[b] = now_ns();
         if (any_lat) {
             const uint32_t n = s->lat_streams;
@@ -1351,6 +1353,8 @@ int mickey_server_step(mickey_server *s)
         }
         if (any_lat && hipStreamWaitEvent(s->stream, s->ev_join, 0) != hipSuccess) return check_launch("latency join");
         hipLaunchKernelGGL(publish_count_kernel, dim3(1), dim3(64), 0, s->stream, s->done_count + b, s->hcount_dev + b);
+        rc = check_launch("publish_count_kernel");
+        if (rc != MICKEY_OK) return rc;
         if (hipEventRecord(s->ev[b], s->stream) != hipSuccess) return check_launch("completion count");
         s->next_q++;
         s->steps++;
