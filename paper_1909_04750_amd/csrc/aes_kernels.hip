@@ -185,9 +185,15 @@ __device__ __forceinline__ void mix_add(uint32_t (&st)[16][8], const uint8_t *rk
     }
 }
 
+// First-round S-box outputs of the nonce bytes, word 8k + b (byte k, bit b) of each lane.
+// They are constant for the call and read once per block, so they live in LDS (16 KiB per
+// 64-lane workgroup, 128 KiB per CU at two waves per SIMD): held in registers beside a
+// round's working set, they were spilled to scratch and reloaded every block.
+using PreLds = uint32_t[64][64];
+
 // One block for the slice: counter block N_i || J under round keys rk (176 bytes);
-// pre[k] (k < 8) are the first-round S-box outputs of the nonce bytes.
-__device__ __forceinline__ void encrypt_block(uint32_t (&st)[16][8], const uint32_t (&pre)[8][8], uint64_t J,
+// pre[8k + b][lane] (k < 8) are the first-round S-box outputs of the nonce bytes.
+__device__ __forceinline__ void encrypt_block(uint32_t (&st)[16][8], const PreLds &pre, uint32_t lane, uint64_t J,
                                               const uint8_t *rk)
 {
     // round 1: SubBytes of byte k lands at the ShiftRows position of k
@@ -197,7 +203,7 @@ __device__ __forceinline__ void encrypt_block(uint32_t (&st)[16][8], const uint3
         const int src = r + 4 * ((c + r) % 4);
         if (src < 8) {
 #pragma unroll
-            for (int b = 0; b < 8; b++) st[k][b] = pre[src][b];
+            for (int b = 0; b < 8; b++) st[k][b] = pre[8 * src + b][lane];
         } else {
             const uint32_t v = kSbox.v[(uint32_t)((J >> (8 * (15 - src))) & 0xFF) ^ rk[src]];
 #pragma unroll
@@ -213,19 +219,22 @@ __device__ __forceinline__ void encrypt_block(uint32_t (&st)[16][8], const uint3
     sub_shift<true>(st, rk + 160);
 }
 
-// First-round S-box outputs of the nonce bytes: SubBytes(N_i ^ k0), bytes 0..7.
-__device__ __forceinline__ void nonce_round1(uint32_t (&pre)[8][8], const uint32_t *planes, size_t pitch_words,
+// First-round S-box outputs of the nonce bytes: SubBytes(N_i ^ k0), bytes 0..7, into this
+// lane's column of pre (only the lane itself reads it back).
+__device__ __forceinline__ void nonce_round1(PreLds &pre, uint32_t lane, const uint32_t *planes, size_t pitch_words,
                                              uint32_t g, const uint8_t *rk)
 {
 #pragma unroll
     for (int k = 0; k < 8; k++) {
-        uint32_t u[8], zero[8];
+        uint32_t u[8], zero[8], o[8];
 #pragma unroll
         for (int b = 0; b < 8; b++) {
             u[b] = planes[(size_t)(8 * k + b) * pitch_words + g] ^ key_mask(rk[k], b);
             zero[b] = 0u;
         }
-        aesbs::sbox<false>(u, pre[k], zero);
+        aesbs::sbox<false>(u, o, zero);
+#pragma unroll
+        for (int b = 0; b < 8; b++) pre[8 * k + b][lane] = o[b];
     }
 }
 
@@ -234,16 +243,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     const uint32_t *__restrict__ nonce_planes, const uint8_t *__restrict__ rk, uint32_t nslices, uint64_t j0,
     uint64_t nblocks, uint32_t *__restrict__ out)
 {
-    const uint32_t g = blockIdx.x * 64u + threadIdx.x;
+    __shared__ PreLds pre;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t g = blockIdx.x * 64u + lane;
     if (g >= nslices) return;
-    uint32_t pre[8][8];
-    nonce_round1(pre, nonce_planes, nslices, g, rk);
+    nonce_round1(pre, lane, nonce_planes, nslices, g, rk);
     const size_t pitch = (size_t)nslices * 4u;
     const uint32_t voff = g * 4u;
     char *plane = (char *)out;  // wave-uniform
     for (uint64_t jb = 0; jb < nblocks; jb++) {
         uint32_t st[16][8];
-        encrypt_block(st, pre, j0 + jb, rk);
+        encrypt_block(st, pre, lane, j0 + jb, rk);
 #pragma unroll
         for (int k = 0; k < 16; k++)
 #pragma unroll
@@ -262,10 +272,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     const uint32_t *__restrict__ nonce_planes, const uint8_t *__restrict__ rk, uint32_t nslices, uint32_t n,
     uint64_t j0, uint64_t nblocks, uint32_t *__restrict__ out_u32, float *__restrict__ out_f32)
 {
-    const uint32_t g = blockIdx.x * 64u + threadIdx.x;
+    __shared__ PreLds pre;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t g = blockIdx.x * 64u + lane;
     if (g >= nslices) return;
-    uint32_t pre[8][8];
-    nonce_round1(pre, nonce_planes, nslices, g, rk);
+    nonce_round1(pre, lane, nonce_planes, nslices, g, rk);
     const uint32_t first = 32u * g;
     const uint32_t valid = n > first ? (n - first < 32u ? n - first : 32u) : 0u;
     const size_t nwords = (size_t)nblocks * 4u;
@@ -273,7 +284,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     float *of = out_f32 ? out_f32 + (size_t)first * nwords : nullptr;
     for (uint64_t jb = 0; jb < nblocks; jb++) {
         uint32_t st[16][8];
-        encrypt_block(st, pre, j0 + jb, rk);
+        encrypt_block(st, pre, lane, j0 + jb, rk);
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             uint32_t a[32];
