@@ -51,6 +51,63 @@ def traffic_record(kernel: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def oracle_threads() -> int:
+    """Host threads the oracle may use: the CPUs this process may run on, at most 16 (the
+    host's share for one GPU)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover - non-Linux
+        avail = os.cpu_count() or 1
+    return max(1, min(avail, 16))
+
+
+class OracleRuns:
+    """cpu_baseline leg: the oracle (plain bit-serial C) run on host threads beside the GPU
+    legs, one instance per job, from its initialisation.  Its outputs also check sampled
+    GPU results of the batched and served configurations bit for bit; its thread time gives
+    the oracle's rate on those configurations."""
+
+    def __init__(self, threads: int):
+        import threading
+        from concurrent.futures import ThreadPoolExecutor
+        import oracle
+        self.oracle = oracle
+        self.threads = threads
+        self.pool = ThreadPoolExecutor(max_workers=threads)
+        self.lock = threading.Lock()
+        self.stats = {}  # tag -> [jobs, bits, thread seconds]
+
+    def stream(self, tag: str, key, iv, iv_bits, nbits: int):
+        """Future of instance (key, iv, iv_bits)'s first nbits keystream bits (MSB-first bytes)."""
+        def job():
+            t0 = time.perf_counter()
+            rows = self.oracle.generate_many(key[None, :], iv[None, :],
+                                             None if iv_bits is None else np.array([iv_bits], dtype=np.uint8),
+                                             int(nbits))
+            dt = time.perf_counter() - t0
+            with self.lock:
+                st = self.stats.setdefault(tag, [0, 0, 0.0])
+                st[0] += 1
+                st[1] += int(nbits)
+                st[2] += dt
+            return rows[0].tobytes()
+        return self.pool.submit(job)
+
+    def rate(self, tag: str):
+        jobs, bits, ts = self.stats.get(tag, [0, 0, 0.0])
+        return {"instances": jobs, "bits": bits, "thread_s": round(ts, 2),
+                "gbit_s_per_core": round(bits / ts / 1e9, 6) if ts else None}
+
+    def close(self):
+        self.pool.shutdown(wait=True)
+
+
+def words_be_bytes(words: np.ndarray) -> bytes:
+    """Row-major words as the oracle's MSB-first byte stream (bit 31-b of word j is bit
+    32j+b, so a word's big-endian bytes are 4 consecutive stream bytes)."""
+    return np.ascontiguousarray(words, dtype=np.uint32).astype(">u4").tobytes()
+
+
 def cpu_baseline(keys, ivs, nbits, gpu_sample_bits, sample_idx, threads):
     """The oracle (plain bit-serial C) on a bounded sample of the same workload."""
     import oracle
@@ -64,11 +121,34 @@ def cpu_baseline(keys, ivs, nbits, gpu_sample_bits, sample_idx, threads):
         "value": round(len(sample_idx) * nbits / dt / 1e9, 6),
         "unit": "Gbit/s",
         "cores": threads,
+        "host_cores": os.cpu_count(),
         "kind": "oracle",
-        "sample": "%d of the %d instances (init + %d keystream bits each), %.1f s wall"
-                  % (len(sample_idx), keys.shape[0], nbits, dt),
+        "sample": "%d of the %d instances (init + %d keystream bits each), %.1f s wall on %d threads "
+                  "(the host's CPU share for one GPU; os.cpu_count() gives the machine's)"
+                  % (len(sample_idx), keys.shape[0], nbits, dt, threads),
         "sample_bit_exact_vs_gpu": match,
     }
+
+
+def cpu_baseline_c1(torch, mickey, synth, threads):
+    """The small configuration in full: 1024 instances x 4096 bits on the GPU (bit-planes)
+    and on the oracle, compared bit for bit, with the oracle's time."""
+    import oracle
+    seed, n, nbits, _ = synth.workload("plain-1k")
+    keys, ivs = synth.keys_ivs(seed, n)
+    m = mickey.Mickey(torch.from_numpy(keys).cuda(), torch.from_numpy(ivs).cuda())
+    out = m.generate(nbits)
+    torch.cuda.synchronize()
+    planes = out.cpu().numpy().reshape(nbits, m.pitch)
+    m.close()
+    got = np.unpackbits(planes, axis=1, bitorder="little")[:, :n].T
+    t0 = time.perf_counter()
+    rows = oracle.generate_many(keys, ivs, None, nbits, threads=threads)
+    dt = time.perf_counter() - t0
+    want = np.unpackbits(rows, axis=1)[:, :nbits]
+    return {"workload": "plain-1k: 1024 instances (seed 1), full init, 4096 bits each", "instances": n,
+            "bits": n * nbits, "oracle_s": round(dt, 3), "gbit_s": round(n * nbits / dt / 1e9, 6),
+            "threads": threads, "bit_exact_vs_gpu": bool((got == want).all())}
 
 
 def bench_rowmajor(torch, mickey, synth, reps: int = 3):
@@ -193,15 +273,25 @@ def bench_aes(torch, mickey, synth, reps: int = 3):
             "hbm_frac": round(bits / 8 / (tg * 1e-3) / 8e12, 4)}
 
 
-def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 12):
+def bench_batch(torch, mickey, synth, oracle_runs=None, tune_cap_bits: int = 4096, nsample: int = 12,
+                n_longest: int = 16, n_other: int = 48):
     """10,000 fresh requests (seed 4): IV lengths 0..80, lengths log-uniform in
     [2^8, 2^24) bits; one persistent work-queue launch replayed from a HIP graph,
     autotuned; compared with per-request plain launches (timed on a sample of requests
     and extrapolated linearly in length) and with the critical path: the longest request
-    alone in latency mode."""
+    alone in latency mode.  With oracle_runs, the n_longest longest requests (all routed to
+    latency mode) and n_other seeded others are checked bit for bit against the oracle,
+    which runs on host threads while the GPU works, after both the routed and the
+    all-bitsliced run."""
     import tempfile
     keys, ivs, ivb, nbits = synth.batch_requests(4, 10000)
     n = len(nbits)
+    check = None
+    if oracle_runs is not None:
+        order = np.argsort(-nbits.astype(np.int64), kind="stable")
+        rng = np.random.default_rng(404)
+        check = np.concatenate([order[:n_longest], rng.choice(order[n_longest:], n_other, replace=False)])
+        want = {int(i): oracle_runs.stream("batch", keys[i], ivs[i], int(ivb[i]), int(nbits[i])) for i in check}
     dk, dv, db = (torch.from_numpy(a).cuda() for a in (keys, ivs, ivb))
     words = (nbits // 32).astype(np.int64)
     offs = np.concatenate([[0], np.cumsum(words)])
@@ -222,10 +312,17 @@ def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 
         e1.record(bs)
         b.sync()
         return e0.elapsed_time(e1)
+    def sample_words():
+        return {} if check is None else {int(i): arena[int(offs[i]):int(offs[i + 1])].cpu().numpy().view(np.uint32)
+                                         for i in check}
+    arena.zero_()
     batch_ms = timed_run()  # size-aware routing (automatic threshold)
+    got_routed = sample_words()
     routing = b.routing()
     b.set_latency_threshold(mickey.Batch.LATENCY_OFF)
+    arena.zero_()
     bs_only_ms = timed_run()  # every request bitsliced
+    got_bs = sample_words()
     b.close()
     del arena
     total_bits = int(nbits.sum())
@@ -273,6 +370,24 @@ def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 
         lat_alone.append(e0.elapsed_time(e1))
     b1.close()
     lat_bound_ms = float(min(lat_alone[1:]))  # the first run builds the graph
+    verified = None
+    if check is not None:
+        mism = 0
+        lat_checked = 0
+        for i in check:
+            w = want[int(i)].result()
+            ok_r = words_be_bytes(got_routed[int(i)]) == w
+            ok_b = words_be_bytes(got_bs[int(i)]) == w
+            mism += int(not ok_r) + int(not ok_b)
+            lat_checked += int(routing[0] is not None and int(nbits[i]) >= routing[0])
+        verified = {"requests": int(len(check)), "outputs_compared": int(2 * len(check)), "mismatches": mism,
+                    "latency_mode_requests": lat_checked,
+                    "bits_per_run": int(nbits[check].sum()),
+                    "sample": "the %d longest requests (%d..%d bits) and %d seeded others, full length, after "
+                              "the routed run and after the all-bitsliced run, against the oracle"
+                              % (n_longest, int(nbits[check[n_longest - 1]]), int(nbits[check[0]]), n_other)}
+        print("# batch-10k oracle check: %d outputs, %d mismatches" % (2 * len(check), mism), file=sys.stderr,
+              flush=True)
     return {"workload": "10,000 fresh requests (splitmix64 seed 4), IV lengths 0..80, lengths log-uniform in "
                         "[2^8, 2^24) bits, row-major u32 outputs, one persistent launch (HIP graph)",
             "requests": n, "total_bits": total_bits, "batch_ms": round(batch_ms, 2),
@@ -294,23 +409,49 @@ def bench_batch(torch, mickey, synth, tune_cap_bits: int = 4096, nsample: int = 
                                       "batch's load does, so the batch can end below the lone run"},
             "per_request_plain": {"sampled": len(ts), "fit_ms": [round(icpt, 4), round(slope * 1e6, 4)],
                                   "fit_units": ["ms", "ns per bit"], "extrapolated_serial_ms": round(serial_ms, 1),
-                                  "batch_speedup": round(serial_ms / batch_ms, 1)}}
+                                  "batch_speedup": round(serial_ms / batch_ms, 1)},
+            "oracle_check": verified}
+
+
+def serve_check_states(sids, nbits, lat_bits: int, n_resumed: int = 48, n_long: int = 16,
+                       resumed_cap_bits: int = 16 << 23, long_cap_bits: int = 24 << 23, seed: int = 505):
+    """States of the served trace whose complete request histories the oracle replays:
+    n_resumed seeded states with at least two requests (a history of at most
+    resumed_cap_bits), and n_long seeded states with a request of at least lat_bits (one
+    that may take a latency stream; a history of at most long_cap_bits)."""
+    order = np.argsort(sids, kind="stable")
+    ss = sids[order]
+    starts = np.flatnonzero(np.r_[True, ss[1:] != ss[:-1]])
+    ends = np.r_[starts[1:], len(ss)]
+    total = np.add.reduceat(nbits[order].astype(np.int64), starts)
+    biggest = np.maximum.reduceat(nbits[order].astype(np.int64), starts)
+    count = ends - starts
+    rng = np.random.default_rng(seed)
+    res = np.flatnonzero((count >= 2) & (total <= resumed_cap_bits) & (biggest < lat_bits))
+    lng = np.flatnonzero((biggest >= lat_bits) & (total <= long_cap_bits))
+    pick = np.concatenate([rng.choice(res, min(n_resumed, len(res)), replace=False),
+                           rng.choice(lng, min(n_long, len(lng)), replace=False)])
+    return {int(ss[starts[g]]): order[starts[g]:ends[g]] for g in pick}  # state -> request ids in arrival order
 
 
 def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: float, qclocks: int = 8192,
                 lat_ratio: int = 4,
                 lat_streams: int = 16384, lat_threshold: int = 1 << 26, rate: float = 20000.0,
                 nstates: int = 10 ** 6, budget: int = 64 << 30, chunk: int = 64 << 10, sat_seconds: float = 3.0,
-                nverify: int = 16):
+                oracle_runs=None):
     """Served generation over 10^6 resident states (splitmix64 seed 5 keys and 80-bit
     IVs, initialised).  Open loop: Poisson arrivals at `rate`/s for `duration` s, state
     uniform, size log-uniform in [4 KiB, max_bytes], delivered in `chunk`-byte chunks
     through a `budget`-byte output budget; latency = completion of the last chunk -
     scheduled arrival.  The run stops when every request is done or `drain` s after the
     last arrival; requests still running then are censored (their latency is only known
-    to exceed the time they have waited).  Closed loop (saturation): every state keeps one
-    request of the same size distribution in flight, chunked through the same budget, for
-    sat_seconds; compared with the plain kernel on the same 10^6 instances."""
+    to exceed the time they have waited).  With oracle_runs, the complete request
+    histories of sampled states (serve_check_states) are replayed by the oracle on host
+    threads during the run and compared with the delivered chunks by digest.  Closed loop
+    (saturation): every state keeps one request of the same size distribution in flight,
+    chunked through the same budget, for sat_seconds, with its per-request latency and
+    per-chunk delivery gaps; compared with the plain kernel on the same 10^6 instances."""
+    import hashlib
     keys, ivs = synth.keys_ivs(5, nstates)
     dk, dv = torch.from_numpy(keys).cuda(), torch.from_numpy(ivs).cuda()
     init = mickey.Mickey(dk, dv)
@@ -319,11 +460,25 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
     # -- open loop
     t_arr, sids, nbits = synth.serve_requests(5, nstates, rate, duration, 4096, max_bytes)
     n = len(t_arr)
-    # sampled for the bit-exact check: first requests on their state, at most 256 KiB
-    first = np.unique(sids, return_index=True)[1]
-    cand = first[nbits[first] <= 8 * (256 << 10)]
-    verify = set(np.sort(cand)[:: max(1, len(cand) // nverify)][:nverify].tolist())
-    vwords = {k: [] for k in verify}
+    hist = serve_check_states(sids, nbits, lat_threshold) if oracle_runs is not None else {}
+    want = {}  # request id -> future of its oracle digest
+
+    def digests(fut, ids):
+        data = fut.result()
+        res, off = {}, 0
+        for r in ids:
+            nb = int(nbits[r]) // 8
+            res[int(r)] = hashlib.blake2b(data[off:off + nb], digest_size=16).digest()
+            off += nb
+        return res
+    hist_futs = []
+    for sid, ids in hist.items():
+        f = oracle_runs.stream("serve", keys[sid], ivs[sid], None, int(nbits[ids].sum()))
+        hist_futs.append((f, ids))
+    vreq = {int(r): sid for sid, ids in hist.items() for r in ids}
+    hashers = {r: hashlib.blake2b(digest_size=16) for r in vreq}
+    next_word = {r: 0 for r in vreq}
+    order_ok = True
     nslices = 32768
     srv = mickey.Server(init, nslices=nslices, quantum_clocks=qclocks, budget_bytes=budget)
     srv.set_chunk(chunk)
@@ -340,6 +495,7 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
     peak_running = 0
     t_stop = duration + drain
     next_note = 5.0
+    vkeys = np.array(sorted(vreq), dtype=np.uint64)
     while done_n < n:
         now = (time.monotonic_ns() - t0) * 1e-9
         if now > t_stop:
@@ -355,10 +511,14 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
         ch = srv.poll_chunks(1 << 16)
         if len(ch):
             nchunks += len(ch)
-            for c in ch[np.isin(ch["request"], list(verify))] if verify else ():
-                buf = torch.empty(int(c["words"]), dtype=torch.int32, device="cuda")
-                srv.copy_chunk(int(c["handle"]), buf, int(c["words"]))
-                vwords[int(c["request"])].append((int(c["offset"]), buf.cpu().numpy().view(np.uint32)))
+            if len(vkeys):
+                for c in ch[np.isin(ch["request"], vkeys)]:
+                    r, w = int(c["request"]), int(c["words"])
+                    buf = torch.empty(w, dtype=torch.int32, device="cuda")
+                    srv.copy_chunk(int(c["handle"]), buf, w)
+                    order_ok &= int(c["offset"]) == next_word[r]
+                    next_word[r] += w
+                    hashers[r].update(words_be_bytes(buf.cpu().numpy().view(np.uint32)))
             srv.release_chunks(ch["handle"])  # the consumer has taken the chunk
         ids = srv.poll(1 << 16)
         if len(ids):
@@ -373,6 +533,7 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
             srv.wait()
     t_end = time.monotonic_ns()
     st = srv.stats()
+    lat_words = srv.latency_words_many(vkeys) if len(vkeys) else np.zeros(0, dtype=np.uint64)
     srv.close()
     span = (t_end - t0) * 1e-9
     done = np.isfinite(lat)
@@ -386,22 +547,38 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
     # per-request stream rate (bits / (completion - admission)) of completed requests of >= 1 MiB
     big = done & (nbits >= 8 * (1 << 20))
     rate_mbit = round(float(np.median(nbits[big] / run_s[big])) / 1e6, 3) if big.any() else None
-    # sampled requests (first request on their state) against the plain kernel run from the
-    # same keys and IVs (the plain path is the one tested bit-exact against the oracle)
-    checked = mism = 0
-    vk = sorted(k for k in verify if done[k])
-    if vk:
-        ln = int(max(nbits[k] for k in vk))
-        ref = mickey.Mickey(torch.from_numpy(keys[sids[vk]]).cuda(), torch.from_numpy(ivs[sids[vk]]).cuda())
-        rbuf = torch.empty((len(vk), ln // 32), dtype=torch.int32, device="cuda")
-        ref.generate(ln, mickey.ROWMAJOR_U32, rbuf)
-        ref.sync()
-        want_all = rbuf.cpu().numpy().view(np.uint32)
-        ref.close()
-        for j, k in enumerate(vk):
-            words = np.concatenate([w for _, w in sorted(vwords[k], key=lambda t: t[0])])
-            checked += 1
-            mism += int(not np.array_equal(words, want_all[j, : int(nbits[k]) // 32]))
+    verified = None
+    if hist:
+        t_wait = time.perf_counter()
+        want = {}
+        for f, ids in hist_futs:
+            want.update(digests(f, ids))
+        wait_s = time.perf_counter() - t_wait
+        lw = {int(r): int(v) for r, v in zip(vkeys, lat_words)}
+        checked = mism = resumed = on_lat = 0
+        for sid, ids in hist.items():
+            for pos, r in enumerate(ids):
+                r = int(r)
+                if not done[r]:
+                    break  # later requests of the state wait for this one
+                checked += 1
+                resumed += int(pos > 0)
+                on_lat += int(lw[r] > 0)
+                mism += int(hashers[r].digest() != want[r])
+        verified = {"states": len(hist), "requests_checked": checked, "mismatches": mism,
+                    "resumed_requests": resumed, "latency_stream_requests": on_lat,
+                    "chunks_in_order": bool(order_ok), "bits_replayed": int(sum(int(nbits[ids].sum())
+                                                                              for ids in hist.values())),
+                    "oracle_wait_after_run_s": round(wait_s, 2),
+                    "sample": "complete request histories of %d seeded states (%d with two or more requests, "
+                              "%d with a request of >= %d KiB), replayed by the oracle on host threads during "
+                              "the run; each completed request's delivered words compared with the oracle's by "
+                              "a 128-bit BLAKE2b digest" % (len(hist), sum(1 for v in hist.values() if len(v) > 1),
+                                                             sum(1 for v in hist.values()
+                                                                 if int(nbits[v].max()) >= lat_threshold),
+                                                             lat_threshold >> 13)}
+        print("# serve open loop oracle check: %d requests (%d resumed, %d on latency streams), %d mismatches"
+              % (checked, resumed, on_lat, mism), file=sys.stderr, flush=True)
     out["open_loop"] = {
         "workload": "10^6 resident states; Poisson arrivals %.0f/s for %.1f s; state uniform; size log-uniform "
                     "4 KiB..%d KiB; row-major u32 output delivered in %d KiB chunks; 64 GiB output budget; "
@@ -421,9 +598,7 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
                    "admitting": round(st["host_admit_ns"] * 1e-9, 3)},
         "chunks": nchunks, "peak_running": peak_running, "steps": st["steps"],
         "mean_quantum_ms": round(st["quantum_ns"] / max(st["steps"], 1) / 1e6, 3),
-        "same_as_plain_kernel_sample": {"requests": checked, "mismatches": mism,
-                                        "sample": "first request on its state, at most 256 KiB, spread over the "
-                                                  "arrivals, compared with the plain row-major kernel"},
+        "oracle_check": verified,
     }
     print("# serve open loop: %d/%d requests done, p50 %s s p99 %s s (lower bound %.1f s)" % (
         int(done.sum()), n, p50, p99, p99_lb), file=sys.stderr, flush=True)
@@ -451,6 +626,8 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
         b0 = tb0 = st0 = c0 = None
         nchunks = 0
         k = 0
+        last_t = np.zeros(len(sid_of), dtype=np.int64)  # request id -> when its last chunk was polled
+        gaps, req_lat = [], []
         while True:
             if k < len(groups):
                 new = srv.submit_many(groups[k], sizes(len(groups[k])))
@@ -458,15 +635,25 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
                 k += 1
             srv.step()
             ch = srv.poll_chunks(1 << 20)
+            t_poll = time.monotonic_ns()
             if len(ch):
                 nchunks += len(ch)
+                r = ch["request"].astype(np.int64)
+                if b0 is not None:  # delivery gaps between consecutive chunks of a request
+                    prev = last_t[r]
+                    gaps.append((t_poll - prev[prev > 0]) * 1e-9)
+                last_t[r] = t_poll
                 srv.release_chunks(ch["handle"])  # the consumer has taken the chunk
             ids = srv.poll(1 << 20)
             if len(ids):
+                if b0 is not None:  # submission to completion of the last chunk
+                    tm = srv.times_many(ids)
+                    req_lat.append((tm[:, 2].astype(np.float64) - tm[:, 0].astype(np.float64)) * 1e-9)
                 again = sid_of[ids]
                 new = srv.submit_many(again, sizes(len(again)))
                 if new.max() >= len(sid_of):
                     sid_of = np.concatenate([sid_of, np.zeros_like(sid_of)])
+                    last_t = np.concatenate([last_t, np.zeros_like(last_t)])
                 sid_of[new] = again
             el = (time.monotonic_ns() - t_start) * 1e-9
             st = srv.stats()
@@ -480,7 +667,17 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
 
         def d(key):
             return (st1[key] - st0[key]) * 1e-9
+        g = np.concatenate(gaps) if gaps else np.zeros(0)
+        rl = np.concatenate(req_lat) if req_lat else np.zeros(0)
+
+        def q(a, p):
+            return round(float(np.percentile(a, p)), 4) if len(a) else None
         return {"served_gbit_s": round((b1 - b0) / win / 1e9, 3), "window_s": round(win, 3),
+                "latency_s": {"chunk_gap_p50": q(g, 50), "chunk_gap_p99": q(g, 99), "chunk_gaps": int(len(g)),
+                              "request_p50": q(rl, 50), "request_p99": q(rl, 99), "requests_completed": int(len(rl)),
+                              "note": "chunk gap: time between deliveries of consecutive 64 KiB chunks of a "
+                                      "request (the stream's latency under load); request: submission to last "
+                                      "chunk, for requests completed in the window"},
                 "chunks_per_s": round((nchunks - c0) / win), "steps_in_window": st1["steps"] - st0["steps"],
                 "device_s_in_window": round(d("gpu_ns"), 3),
                 "host_s_in_window": {"blocked_on_gpu": round(d("host_wait_ns"), 3),
@@ -515,7 +712,8 @@ def bench_serve(torch, mickey, synth, duration: float, max_bytes: int, drain: fl
         "note": "the same loop with every first request submitted at once: all lanes finish their 64 KiB "
                 "chunks in the same quanta, and the host's retirement of those bursts idles the device",
         "served_gbit_s": sync["served_gbit_s"], "served_over_plain": round(sync["served_gbit_s"] / plain, 4),
-        "device_s_in_window": sync["device_s_in_window"], "window_s": sync["window_s"]}
+        "device_s_in_window": sync["device_s_in_window"], "window_s": sync["window_s"],
+        "latency_s": sync["latency_s"]}
     print("# serve closed loop: %.1f Gbit/s served vs %.1f plain (synchronized start: %.1f)" % (
         served, plain, sync["served_gbit_s"]), file=sys.stderr, flush=True)
     return out
@@ -535,7 +733,7 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true", help="skip the served measurements")
     ap.add_argument("--no-grain", action="store_true", help="skip the bitsliced Grain leg")
     ap.add_argument("--no-aes", action="store_true", help="skip the bitsliced AES-CTR leg")
-    ap.add_argument("--serve-seconds", type=float, default=2.0, help="Poisson arrival window of the served run")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="Poisson arrival window of the served run")
     ap.add_argument("--serve-max-kib", type=int, default=64 << 10, help="largest served request (KiB)")
     ap.add_argument("--serve-drain", type=float, default=90.0,
                     help="seconds the open-loop served run continues after the last arrival")
@@ -675,8 +873,9 @@ def main() -> int:
         ti = torch.from_numpy(sample_idx // 8).cuda()
         sh = torch.from_numpy(sample_idx % 8).cuda().to(torch.uint8)
         gpu_bits = ((planes[:, ti] >> sh) & 1).T.cpu().numpy()
-        threads = min(os.cpu_count() or 1, 16)
+        threads = oracle_threads()
         res["cpu_baseline"] = cpu_baseline(keys, ivs, nbits, gpu_bits, sample_idx, threads)
+        res["cpu_baseline"]["c1_full"] = cpu_baseline_c1(torch, mickey, synth, threads)
 
     m.close()
     del out
@@ -687,12 +886,22 @@ def main() -> int:
         res["grain_4m"] = bench_grain(torch, mickey, synth)
     if not args.no_aes:
         res["aes_4m"] = bench_aes(torch, mickey, synth)
+    # the oracle's runs on sampled batched and served requests (part of the cpu_baseline leg)
+    # go on host threads while the GPU works; they also check those requests' outputs
+    # (half the host threads: the server's host loop and the GPU runtime need the rest)
+    oruns = None if args.no_cpu_baseline else OracleRuns(max(1, oracle_threads() // 2))
     if not args.no_batch:
-        res["batch_10k"] = bench_batch(torch, mickey, synth)
+        res["batch_10k"] = bench_batch(torch, mickey, synth, oracle_runs=oruns)
     if not args.no_serve:
         res["serve"] = bench_serve(torch, mickey, synth, args.serve_seconds, args.serve_max_kib << 10,
                                    args.serve_drain, args.serve_quantum, args.serve_lat_ratio, args.serve_lat_streams,
-                                   args.serve_lat_kib << 13)
+                                   args.serve_lat_kib << 13, oracle_runs=oruns)
+    if oruns is not None:
+        oruns.close()
+        if "cpu_baseline" in res:
+            res["cpu_baseline"]["batch_10k_sample"] = oruns.rate("batch")
+            res["cpu_baseline"]["serve_sample"] = oruns.rate("serve")
+            res["cpu_baseline"]["sample_threads"] = oruns.threads
     print(json.dumps(res), flush=True)
     return 0
 

@@ -40,8 +40,14 @@
  *
  * Errors: functions return MICKEY_OK (0) or a negative code; mickey_init returns NULL
  * on error.  mickey_last_error() gives the calling thread's last code and
- * mickey_last_error_message() a description.  A failed call leaves the state and its
- * bit counter unchanged.
+ * mickey_last_error_message() a description.  A call on a state that fails leaves its
+ * registers and bit counters as they were (a call made of several launches that change
+ * the registers first copies them and copies them back if a later launch fails); the
+ * contents of its output buffers are then unspecified.  If even that copy cannot be
+ * enqueued, or mickey_sync() reports a device failure, the state is poisoned: every
+ * later call on it returns MICKEY_EDEVICE, except mickey_free, the queries, a re-key or
+ * an import (which replace all registers), and export, which then gives the registers
+ * saved before the call that failed when they exist.
  */
 #ifndef MICKEY_H
 #define MICKEY_H
@@ -56,8 +62,8 @@ extern "C" {
 #define MICKEY_OK 0
 #define MICKEY_EINVAL (-1)  /* bad argument: NULL pointer, n == 0, IV length > 80, layout */
 #define MICKEY_ENOMEM (-2)  /* device allocation failed */
-#define MICKEY_EDEVICE (-3) /* a HIP call or kernel launch failed */
-#define MICKEY_ERANGE (-4)  /* more than 2^40 keystream bits for one key/IV pair */
+#define MICKEY_EDEVICE (-3) /* a HIP call or kernel launch failed, or the state is poisoned */
+#define MICKEY_ERANGE (-4)  /* more than 2^40 keystream bits for one key/IV pair (Sec. II-C-1) */
 #define MICKEY_ENOSYS (-5)  /* unsupported combination (e.g. word width) */
 
 #define MICKEY_BITSLICED 0
@@ -103,7 +109,30 @@ int mickey_generate(mickey_state *st, uint64_t nbits, void *out, int layout);
  * and MICKEY_ROWMAJOR_F32.  nbits % 32 == 0. */
 int mickey_generate_rowmajor(mickey_state *st, uint64_t nbits, uint32_t *out_u32, float *out_f32);
 
-/* Release the state (synchronises its stream first).  NULL is allowed. */
+/* Per-instance requests (the paper's problem statement, Sec. IV-D: independent instances,
+ * each with its own key and IV).  Request k resumes instance reqs[k].instance of `st` for
+ * reqs[k].nbits keystream bits (a multiple of 32; 0 is allowed and does nothing) and writes
+ * them to reqs[k].out (device, nbits/8 bytes) in reqs[k].layout, which is
+ * MICKEY_ROWMAJOR_U32 (bit 31-b of word j is z_{32j+b} of that instance's stream from where
+ * it stood) or MICKEY_ROWMAJOR_F32 (the same words as exact floats (w >> 8) * 2^-24).
+ * Requests on the same instance are applied in array order: each continues at the bit
+ * after the previous one.  Other instances do not move.  Every request is validated
+ * before any work is enqueued (MICKEY_EINVAL for an instance >= n, another layout, a
+ * length not a multiple of 32 or a NULL output; MICKEY_ERANGE when an instance would pass
+ * 2^40 bits in total or 2^37 bits in this call).  Long per-instance streams run in latency
+ * mode (four lanes per instance), the rest bitsliced; the output bytes do not depend on
+ * that.  Asynchronous on the state's stream; the library's device scratch and a pinned
+ * host staging buffer grow on demand and are kept until mickey_free.  reqs (host) may be
+ * reused when the call returns. */
+typedef struct mickey_req {
+    uint64_t instance; /* 0 .. n-1 */
+    uint64_t nbits;    /* keystream bits, a multiple of 32 */
+    void *out;         /* device, nbits/8 bytes */
+    int layout;        /* MICKEY_ROWMAJOR_U32 or MICKEY_ROWMAJOR_F32 */
+} mickey_req;
+int mickey_generate_batch(mickey_state *st, const mickey_req *reqs, size_t nreq);
+
+/* Release the state (synchronises its streams first).  NULL is allowed. */
 void mickey_free(mickey_state *st);
 
 /* Bind the state to a HIP stream (void* hipStream_t; NULL = null stream). */
@@ -155,8 +184,14 @@ int mickey_set_schedule(mickey_state *st, int schedule);
 int mickey_set_transpose(mickey_state *st, int mode);
 
 size_t mickey_num_instances(const mickey_state *st);
-/* Keystream bits produced so far by each instance of the state. */
+/* Keystream bits every instance has produced through whole-state calls (mickey_generate,
+ * mickey_generate_rowmajor) since the last initialisation or import; instances that
+ * mickey_generate_batch advanced further have their own totals (mickey_instance_bits).
+ * The 2^40 limit of Sec. II-C-1 applies to each instance's total. */
 uint64_t mickey_bits_generated(const mickey_state *st);
+/* Keystream bits instance `instance` has produced in total; UINT64_MAX (and
+ * MICKEY_EINVAL) for a NULL state or an instance >= n. */
+uint64_t mickey_instance_bits(const mickey_state *st, size_t instance);
 /* Bytes per bit-plane of the MICKEY_BITSLICED layout for n instances: 8*ceil(n/64). */
 size_t mickey_plane_pitch(size_t n);
 
@@ -167,12 +202,31 @@ size_t mickey_plane_pitch(size_t n);
 int mickey_state_export(const mickey_state *st, uint8_t *packed, uint64_t *bits_generated);
 
 /* Overwrite every instance's registers from `packed` (device, n*25 bytes, layout as in
- * mickey_state_export) and set the bit counter; generation then resumes from there.
- * Pad instances are left as they are.  Asynchronous. */
+ * mickey_state_export) and set every instance's bit counter to bits_generated
+ * (MICKEY_ERANGE beyond 2^40); generation then resumes from there.  Pad instances are
+ * left as they are.  Asynchronous. */
 int mickey_state_import(mickey_state *st, const uint8_t *packed, uint64_t bits_generated);
 
-/* Wait for all work enqueued on the state's stream. */
+/* Host form of a state, for checkpoints (a state resumes exactly, Sec. II-C-1's per-key/IV
+ * budget included): a 32-byte header (8 bytes "MICKEY2\0", uint32 version 1, uint32 25,
+ * uint64 n, 8 reserved bytes), then the n packed states of mickey_state_export, then n
+ * uint64 bit counters (mickey_instance_bits), all little-endian: mickey_state_host_bytes(st)
+ * = 32 + 33*n bytes (0 for NULL).  Export writes it to `host` (cap bytes, host memory; too
+ * small: MICKEY_EINVAL) and synchronises the state's stream.  Import checks the header, n,
+ * len and every counter before it changes anything (MICKEY_EINVAL / MICKEY_ERANGE), then
+ * replaces every instance's registers and counter, and synchronises the copy to the device. */
+size_t mickey_state_host_bytes(const mickey_state *st);
+int mickey_state_export_host(const mickey_state *st, void *host, size_t cap);
+int mickey_state_import_host(mickey_state *st, const void *host, size_t len);
+
+/* Wait for all work enqueued on the state's streams.  A failure poisons the state. */
 int mickey_sync(mickey_state *st);
+
+/* Failure injection, for testing the error paths without a faulty device: the k-th launch
+ * (kernel or state copy) from now, made by any state of this process, is not made and
+ * its call returns MICKEY_EDEVICE as if the launch had failed; k = 0 cancels a pending
+ * injection.  MICKEY_EINVAL for k < 0. */
+int mickey_debug_fail_launch(int k);
 
 /* ---------------------------------------------------------------------------------
  * Batched generation (one persistent launch for many fresh requests).
@@ -274,6 +328,9 @@ int mickey_server_submit_many(mickey_server *s, const uint32_t *sids, const uint
                               int64_t *ids);
 int mickey_server_release_many(mickey_server *s, const uint64_t *ids, size_t n);
 int mickey_server_times_many(const mickey_server *s, const uint64_t *ids, size_t n, uint64_t *out);
+/* Words of each of n requests (submitted, not necessarily complete) admitted so far to
+ * latency streams (see mickey_server_set_latency) rather than to bit lanes. */
+int mickey_server_latency_words_many(const mickey_server *s, const uint64_t *ids, size_t n, uint64_t *out);
 
 /* One scheduling step: wait for the quantum launched by the previous step and retire
  * the requests it completed, admit waiting requests and gather their states, then launch

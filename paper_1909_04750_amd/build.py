@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "lib")
 LIB_PATH = os.path.join(LIB_DIR, "libmickey.so")
-SOURCES = ["mickey_kernels.hip", "mickey_batch.hip", "mickey_serve.hip", "grain_kernels.hip", "aes_kernels.hip"]
+SOURCES = ["mickey_kernels.hip", "mickey_resume.hip", "mickey_batch.hip", "mickey_serve.hip", "grain_kernels.hip",
+           "aes_kernels.hip"]
 ARCH = "gfx950"
 
 

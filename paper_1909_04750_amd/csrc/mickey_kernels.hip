@@ -11,9 +11,11 @@
 // lanes; no LDS except the row-major transpose staging.
 #include "mickey_device.h"
 #include "mickey_host.h"
+#include "mickey_state.h"
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -409,26 +411,6 @@ __global__ __launch_bounds__(256) void import_kernel(const uint8_t *__restrict__
 
 // ------------------------------------------------------------------------ C ABI
 
-struct mickey_state {
-    size_t n;
-    size_t n_pad;
-    size_t nslices;
-    uint32_t *planes = nullptr;       // device, 200 * nslices words
-    uint32_t *stage = nullptr;        // device, input/mask planes + status word
-    uint32_t *host_status = nullptr;  // pinned host word for the IV length check
-    hipStream_t stream;
-    uint64_t bits;
-    int word_bits;
-    int schedule;   // MICKEY_SCHED_*
-    int transpose;  // MICKEY_TRANSPOSE_*
-    int simds;      // SIMDs of the device (4 per compute unit)
-    int device;
-    uint32_t *chunk = nullptr;  // device, two bit-plane chunk buffers of the staged row-major path
-    uint64_t chunk_clocks = 0;  // capacity of each in clocks (0: not allocated yet)
-    hipStream_t side = nullptr;  // staged transposes run here, overlapping the next chunk
-    hipEvent_t ev_gen[2] = {nullptr, nullptr}, ev_tp[2] = {nullptr, nullptr};
-};
-
 namespace mickey_host {
 
 thread_local int g_err = MICKEY_OK;
@@ -465,6 +447,54 @@ void prefix_error(const char *prefix)
     snprintf(g_msg, sizeof g_msg, "%s: %s", prefix, msg);
 }
 
+// Launches left before an injected failure (0: none pending); see mickey_debug_fail_launch.
+std::atomic<int> g_fail_in{0};
+
+int launch_guard(const char *what)
+{
+    int k = g_fail_in.load();
+    while (k > 0 && !g_fail_in.compare_exchange_weak(k, k - 1)) {
+    }
+    if (k == 1) return fail(MICKEY_EDEVICE, "%s: injected launch failure", what);
+    return MICKEY_OK;
+}
+
+int ensure_side(mickey_state *st)
+{
+    if (st->side) return MICKEY_OK;
+    bool okc = hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking) == hipSuccess;
+    for (int b = 0; b < 2 && okc; b++)
+        okc = hipEventCreateWithFlags(&st->ev_gen[b], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&st->ev_tp[b], hipEventDisableTiming) == hipSuccess;
+    okc = okc && hipEventCreateWithFlags(&st->ev_fork, hipEventDisableTiming) == hipSuccess &&
+          hipEventCreateWithFlags(&st->ev_join, hipEventDisableTiming) == hipSuccess;
+    if (!okc) {
+        (void)hipGetLastError();
+        return fail(MICKEY_EDEVICE, "cannot create the state's second stream or its events");
+    }
+    return MICKEY_OK;
+}
+
+int ensure_scratch(mickey_state *st, size_t bytes)
+{
+    if (st->bmem_bytes >= bytes) return MICKEY_OK;
+    if (st->bmem) {  // work queued earlier may still read it
+        (void)hipStreamSynchronize(st->stream);
+        if (st->side) (void)hipStreamSynchronize(st->side);
+        (void)hipFree(st->bmem);
+        st->bmem = nullptr;
+        st->bmem_bytes = 0;
+    }
+    const size_t want = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
+    if (hipMalloc(&st->bmem, want) != hipSuccess) {
+        (void)hipGetLastError();
+        st->bmem = nullptr;
+        return fail(MICKEY_ENOMEM, "cannot allocate %zu bytes of scratch", want);
+    }
+    st->bmem_bytes = want;
+    return MICKEY_OK;
+}
+
 }  // namespace mickey_host
 
 namespace {
@@ -473,7 +503,9 @@ namespace {
 constexpr size_t kMaxInstances = (size_t)1 << 31;
 
 // a1 + a2 on an allocated state: stage the inputs, run the 260 initialisation clocks,
-// reset the bit counter.  With iv_bits the lengths are validated (stream sync).
+// reset the bit counters.  With iv_bits the lengths are validated (stream sync) after the
+// staging and before the initialisation touches the registers, so a refused length leaves
+// the state as it was.
 int run_init(mickey_state *st, const uint8_t *keys, const uint8_t *ivs, const uint8_t *iv_bits)
 {
     if (!keys || !ivs) return fail(MICKEY_EINVAL, "keys and ivs must be device pointers");
@@ -482,13 +514,23 @@ int run_init(mickey_state *st, const uint8_t *keys, const uint8_t *ivs, const ui
     uint32_t *status = mask_planes + (size_t)kMaskPlanes * st->nslices;
     if (hipMemsetAsync(status, 0, 4, st->stream) != hipSuccess) return check_launch("hipMemsetAsync");
     const dim3 sgrid((unsigned)((st->n_pad + 255) / 256));
+    int rc = launch_guard("stage_kernel");
+    if (rc != MICKEY_OK) return rc;
     if (iv_bits)
         hipLaunchKernelGGL((stage_kernel<true, false>), sgrid, dim3(256), 0, st->stream, keys, ivs, iv_bits,
                            nullptr, (uint32_t)st->n, (uint32_t)st->nslices, in_planes, mask_planes, status);
     else
         hipLaunchKernelGGL((stage_kernel<false, false>), sgrid, dim3(256), 0, st->stream, keys, ivs, iv_bits,
                            nullptr, (uint32_t)st->n, (uint32_t)st->nslices, in_planes, mask_planes, status);
-    int rc = check_launch("stage_kernel");
+    rc = check_launch("stage_kernel");
+    if (rc != MICKEY_OK) return rc;
+    if (iv_bits) {
+        if (hipMemcpyAsync(st->host_status, status, 4, hipMemcpyDeviceToHost, st->stream) != hipSuccess ||
+            hipStreamSynchronize(st->stream) != hipSuccess)
+            return check_launch("IV length check");
+        if (*st->host_status) return fail(MICKEY_EINVAL, "an IV length exceeds 80 bits");
+    }
+    rc = launch_guard("init_kernel");
     if (rc != MICKEY_OK) return rc;
     const dim3 grid((unsigned)((st->nslices + 63) / 64));
     if (iv_bits)
@@ -499,13 +541,11 @@ int run_init(mickey_state *st, const uint8_t *keys, const uint8_t *ivs, const ui
                            (uint32_t)st->nslices);
     rc = check_launch("init_kernel");
     if (rc != MICKEY_OK) return rc;
-    if (iv_bits) {
-        if (hipMemcpyAsync(st->host_status, status, 4, hipMemcpyDeviceToHost, st->stream) != hipSuccess ||
-            hipStreamSynchronize(st->stream) != hipSuccess)
-            return check_launch("IV length check");
-        if (*st->host_status) return fail(MICKEY_EINVAL, "an IV length exceeds 80 bits");
-    }
     st->bits = 0;
+    st->extra.clear();
+    st->max_extra = 0;
+    st->snap_valid = false;
+    st->poisoned = false;
     return MICKEY_OK;
 }
 
@@ -513,15 +553,19 @@ void destroy(mickey_state *st)
 {
     if (!st) return;
     (void)hipStreamSynchronize(st->stream);
+    if (st->side) (void)hipStreamSynchronize(st->side);
     if (st->planes) (void)hipFree(st->planes);
     if (st->stage) (void)hipFree(st->stage);
     if (st->host_status) (void)hipHostFree(st->host_status);
-    if (st->side) (void)hipStreamSynchronize(st->side);
     if (st->chunk) (void)hipFree(st->chunk);
-    for (int b = 0; b < 2; b++) {
-        if (st->ev_gen[b]) (void)hipEventDestroy(st->ev_gen[b]);
-        if (st->ev_tp[b]) (void)hipEventDestroy(st->ev_tp[b]);
-    }
+    if (st->snap) (void)hipFree(st->snap);
+    if (st->bmem) (void)hipFree(st->bmem);
+    if (st->bhost_ev) (void)hipEventSynchronize(st->bhost_ev);
+    if (st->bhost) (void)hipHostFree(st->bhost);
+    hipEvent_t evs[] = {st->ev_gen[0], st->ev_gen[1], st->ev_tp[0], st->ev_tp[1], st->bhost_ev, st->ev_fork,
+                        st->ev_join};
+    for (hipEvent_t e : evs)
+        if (e) (void)hipEventDestroy(e);
     if (st->side) (void)hipStreamDestroy(st->side);
     delete st;
 }
@@ -549,7 +593,7 @@ mickey_state *init_impl(const uint8_t *keys, const uint8_t *ivs, const uint8_t *
     st->word_bits = 32;
     st->schedule = MICKEY_SCHED_AUTO;
     st->transpose = MICKEY_TRANSPOSE_AUTO;
-    hipGetDevice(&st->device);
+    (void)hipGetDevice(&st->device);
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, st->device) != hipSuccess || cus <= 0) {
         (void)hipGetLastError();
@@ -622,24 +666,77 @@ int launch_generate_planes(mickey_state *st, uint64_t nbits, uint32_t *out);
 // instead of 2.07 serially) but not beside the four-wave split, whose waves and the
 // transpose's slow each other down more than they overlap (2.0 ms instead of 1.8): with
 // that schedule the transposes run on the state's stream.
+// The registers are first copied to `snap` (200 planes): if a launch after the first
+// generate fails, they are copied back, so the call fails with the state unchanged; if
+// even that copy cannot be enqueued, the state is poisoned.
+//   chunk: two buffers of chunk_clocks planes each (chunk_clocks a multiple of 1024)
+int generate_staged_with(mickey_state *st, uint64_t nbits, uint32_t *out_u32, float *out_f32, uint32_t *chunk,
+                         uint64_t chunk_clocks, uint32_t *snap)
+{
+    const size_t pitch = st->nslices * 4;
+    int rc = ensure_side(st);
+    if (rc != MICKEY_OK) return rc;
+    rc = launch_guard("state snapshot");
+    if (rc != MICKEY_OK) return rc;
+    if (hipMemcpyAsync(snap, st->planes, 200 * pitch, hipMemcpyDeviceToDevice, st->stream) != hipSuccess)
+        return check_launch("state snapshot");
+    const uint64_t nwords = nbits / 32;
+    hipStream_t tp_stream = use_split4(st) ? st->stream : st->side;
+    int last = 0;
+    uint64_t k = 0;
+    bool changed = false;  // a generate kernel has been launched on the registers
+    for (uint64_t c0 = 0; c0 < nbits && rc == MICKEY_OK; c0 += chunk_clocks, k++) {
+        const int b = (int)(k & 1);
+        uint32_t *buf = chunk + (size_t)b * chunk_clocks * st->nslices;
+        const uint64_t nc = nbits - c0 < chunk_clocks ? nbits - c0 : chunk_clocks;
+        if (k >= 2 && hipStreamWaitEvent(st->stream, st->ev_tp[b], 0) != hipSuccess) {
+            rc = check_launch("hipStreamWaitEvent");
+            break;
+        }
+        rc = launch_generate_planes(st, nc, buf);
+        if (rc != MICKEY_OK) break;
+        changed = true;
+        if (hipEventRecord(st->ev_gen[b], st->stream) != hipSuccess ||
+            hipStreamWaitEvent(tp_stream, st->ev_gen[b], 0) != hipSuccess) {
+            rc = check_launch("hipEventRecord");
+            break;
+        }
+        rc = launch_guard("rowmajor_transpose_kernel");
+        if (rc != MICKEY_OK) break;
+        const dim3 grid((unsigned)((st->nslices + kTpSlices - 1) / kTpSlices),
+                        (unsigned)((nc + kTpClocks - 1) / kTpClocks));
+        hipLaunchKernelGGL(rowmajor_transpose_kernel, grid, dim3(256), 0, tp_stream, buf, (uint32_t)st->nslices,
+                           (uint32_t)nc, (uint32_t)st->n, nwords, c0 / 32, out_u32, out_f32);
+        rc = check_launch("rowmajor_transpose_kernel");
+        if (rc != MICKEY_OK) break;
+        if (hipEventRecord(st->ev_tp[b], tp_stream) != hipSuccess) {
+            rc = check_launch("hipEventRecord");
+            break;
+        }
+        last = b;
+    }
+    if (rc == MICKEY_OK && hipStreamWaitEvent(st->stream, st->ev_tp[last], 0) != hipSuccess)
+        rc = check_launch("hipStreamWaitEvent");
+    if (rc != MICKEY_OK && changed) {
+        // the generate kernels all ran on the state's stream: the copy back follows them
+        if (hipMemcpyAsync(st->planes, snap, 200 * pitch, hipMemcpyDeviceToDevice, st->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            st->poisoned = true;
+            st->snap_valid = snap == st->snap;
+        }
+    }
+    return rc;
+}
+
+// The state's own chunk buffers (allocated on first use, two of `want` clocks) and snapshot.
 int generate_staged(mickey_state *st, uint64_t nbits, uint32_t *out_u32, float *out_f32, uint64_t cc)
 {
     const size_t pitch = st->nslices * 4;
-    if (!st->side) {
-        bool okc = hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking) == hipSuccess;
-        for (int b = 0; b < 2 && okc; b++)
-            okc = hipEventCreateWithFlags(&st->ev_gen[b], hipEventDisableTiming) == hipSuccess &&
-                  hipEventCreateWithFlags(&st->ev_tp[b], hipEventDisableTiming) == hipSuccess;
-        if (!okc) {
-            (void)hipGetLastError();
-            return fail(MICKEY_EDEVICE, "mickey_generate: cannot create the transpose stream or its events");
-        }
-    }
     const uint64_t want = nbits < cc ? (nbits + kTpClocks - 1) / kTpClocks * kTpClocks : cc;
     if (st->chunk_clocks < want) {
         if (st->chunk) {
             (void)hipStreamSynchronize(st->stream);
-            (void)hipStreamSynchronize(st->side);
+            if (st->side) (void)hipStreamSynchronize(st->side);
             (void)hipFree(st->chunk);
             st->chunk = nullptr;
             st->chunk_clocks = 0;
@@ -652,37 +749,19 @@ int generate_staged(mickey_state *st, uint64_t nbits, uint32_t *out_u32, float *
         }
         st->chunk_clocks = want;
     }
-    const uint64_t nwords = nbits / 32;
-    hipStream_t tp_stream = use_split4(st) ? st->stream : st->side;
-    int last = 0;
-    uint64_t k = 0;
-    for (uint64_t c0 = 0; c0 < nbits; c0 += st->chunk_clocks, k++) {
-        const int b = (int)(k & 1);
-        uint32_t *buf = st->chunk + (size_t)b * st->chunk_clocks * st->nslices;
-        const uint64_t nc = nbits - c0 < st->chunk_clocks ? nbits - c0 : st->chunk_clocks;
-        if (k >= 2 && hipStreamWaitEvent(st->stream, st->ev_tp[b], 0) != hipSuccess)
-            return check_launch("hipStreamWaitEvent");
-        int rc = launch_generate_planes(st, nc, buf);
-        if (rc != MICKEY_OK) return rc;
-        if (hipEventRecord(st->ev_gen[b], st->stream) != hipSuccess ||
-            hipStreamWaitEvent(tp_stream, st->ev_gen[b], 0) != hipSuccess)
-            return check_launch("hipEventRecord");
-        const dim3 grid((unsigned)((st->nslices + kTpSlices - 1) / kTpSlices),
-                        (unsigned)((nc + kTpClocks - 1) / kTpClocks));
-        hipLaunchKernelGGL(rowmajor_transpose_kernel, grid, dim3(256), 0, tp_stream, buf, (uint32_t)st->nslices,
-                           (uint32_t)nc, (uint32_t)st->n, nwords, c0 / 32, out_u32, out_f32);
-        rc = check_launch("rowmajor_transpose_kernel");
-        if (rc != MICKEY_OK) return rc;
-        if (hipEventRecord(st->ev_tp[b], tp_stream) != hipSuccess) return check_launch("hipEventRecord");
-        last = b;
+    if (!st->snap && hipMalloc(&st->snap, 200 * pitch) != hipSuccess) {
+        (void)hipGetLastError();
+        st->snap = nullptr;
+        return fail(MICKEY_ENOMEM, "mickey_generate: cannot allocate the %zu-byte state snapshot", 200 * pitch);
     }
-    if (hipStreamWaitEvent(st->stream, st->ev_tp[last], 0) != hipSuccess) return check_launch("hipStreamWaitEvent");
-    return MICKEY_OK;
+    return generate_staged_with(st, nbits, out_u32, out_f32, st->chunk, st->chunk_clocks, st->snap);
 }
 
 // nbits clocks of every instance as bit-planes (pitch nslices*4 bytes) to out.
 int launch_generate_planes(mickey_state *st, uint64_t nbits, uint32_t *out)
 {
+    int rc = launch_guard("gen_bitsliced_kernel");
+    if (rc != MICKEY_OK) return rc;
     const size_t pitch = st->nslices * 4;
     const unsigned nblocks = (unsigned)((st->nslices + 63) / 64);
     if (use_split4(st)) {
@@ -702,29 +781,42 @@ int launch_generate_planes(mickey_state *st, uint64_t nbits, uint32_t *out)
     return check_launch("gen_bitsliced_kernel");
 }
 
-int generate_impl(mickey_state *st, uint64_t nbits, int layout, void *out, uint32_t *out_u32, float *out_f32)
+// Argument and range checks of a whole-state generate (nothing is changed).
+int check_generate(const mickey_state *st, uint64_t nbits, int layout)
 {
     if (!st) return fail(MICKEY_EINVAL, "mickey_generate: NULL state");
+    if (st->poisoned) return fail(MICKEY_EDEVICE, "mickey_generate: the state was lost to an earlier device failure");
     if (nbits == 0) return fail(MICKEY_EINVAL, "mickey_generate: nbits must be >= 1");
-    if (nbits > MICKEY_MAX_BITS_PER_IV || st->bits > MICKEY_MAX_BITS_PER_IV - nbits)
+    if (nbits > MICKEY_MAX_BITS_PER_IV || st->bits + st->max_extra > MICKEY_MAX_BITS_PER_IV - nbits)
         return fail(MICKEY_ERANGE, "mickey_generate: %llu + %llu bits exceeds 2^40 per key/IV pair",
-                    (unsigned long long)st->bits, (unsigned long long)nbits);
+                    (unsigned long long)(st->bits + st->max_extra), (unsigned long long)nbits);
+    if (layout != MICKEY_BITSLICED && nbits % 32 != 0)
+        return fail(MICKEY_EINVAL, "row-major layouts need nbits %% 32 == 0");
+    return MICKEY_OK;
+}
+
+int generate_impl(mickey_state *st, uint64_t nbits, int layout, void *out, uint32_t *out_u32, float *out_f32)
+{
+    int rc = check_generate(st, nbits, layout);
+    if (rc != MICKEY_OK) return rc;
     const bool split = use_split(st);
     const unsigned nblocks = (unsigned)((st->nslices + 63) / 64);
     if (layout == MICKEY_BITSLICED) {
         if (!out) return fail(MICKEY_EINVAL, "mickey_generate: NULL output");
-        int rc = launch_generate_planes(st, nbits, (uint32_t *)out);
+        rc = launch_generate_planes(st, nbits, (uint32_t *)out);
         if (rc != MICKEY_OK) return rc;
     } else {
-        if (nbits % 32 != 0) return fail(MICKEY_EINVAL, "row-major layouts need nbits %% 32 == 0");
         if (!out_u32 && !out_f32) return fail(MICKEY_EINVAL, "mickey_generate: NULL output");
         const uint64_t cc = staged_chunk_clocks(st);
         if (st->transpose == MICKEY_TRANSPOSE_STAGED || (st->transpose == MICKEY_TRANSPOSE_AUTO && cc)) {
-            int rc = generate_staged(st, nbits, out_u32, out_f32, cc ? cc : (uint64_t)kTpClocks);
+            rc = generate_staged(st, nbits, out_u32, out_f32, cc ? cc : (uint64_t)kTpClocks);
             if (rc != MICKEY_OK) return rc;
             st->bits += nbits;
+            st->snap_valid = false;
             return ok();
         }
+        rc = launch_guard("gen_rowmajor_kernel");
+        if (rc != MICKEY_OK) return rc;
         if (split) {
             hipLaunchKernelGGL(gen_split_kernel<true>, dim3(nblocks), dim3(128), 0, st->stream, st->planes,
                                (uint32_t)st->nslices, (uint32_t)st->n, nbits, nullptr, out_u32, out_f32);
@@ -732,12 +824,28 @@ int generate_impl(mickey_state *st, uint64_t nbits, int layout, void *out, uint3
             hipLaunchKernelGGL(gen_rowmajor_kernel, dim3(nblocks), dim3(64), 0, st->stream, st->planes,
                                (uint32_t)st->nslices, (uint32_t)st->n, nbits / 32, out_u32, out_f32);
         }
-        int rc = check_launch("gen_rowmajor_kernel");
+        rc = check_launch("gen_rowmajor_kernel");
         if (rc != MICKEY_OK) return rc;
     }
     st->bits += nbits;
+    st->snap_valid = false;
     return ok();
 }
+
+// Host form of the state (mickey_state_export_host): a 32-byte header, the packed
+// registers of every instance, then every instance's bit counter.
+constexpr char kHostMagic[8] = {'M', 'I', 'C', 'K', 'E', 'Y', '2', 0};
+constexpr uint32_t kHostVersion = 1;
+struct HostHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t state_bytes;
+    uint64_t n;
+    uint64_t reserved;
+};
+static_assert(sizeof(HostHeader) == 32, "host state header is 32 bytes");
+
+size_t host_state_bytes(size_t n) { return sizeof(HostHeader) + n * (25 + 8); }
 
 }  // namespace
 
@@ -779,7 +887,11 @@ int mickey_rekey(mickey_state *st, const uint8_t *keys, const uint8_t *ivs, cons
 {
     if (!st) return fail(MICKEY_EINVAL, "mickey_rekey: NULL state");
     int rc = run_init(st, keys, ivs, iv_bits);
-    return rc == MICKEY_OK ? ok() : rc;
+    if (rc != MICKEY_OK) {
+        prefix_error("mickey_rekey");
+        return rc;
+    }
+    return ok();
 }
 
 void mickey_free(mickey_state *st) { destroy(st); }
@@ -827,14 +939,30 @@ size_t mickey_num_instances(const mickey_state *st) { return st ? st->n : 0; }
 
 uint64_t mickey_bits_generated(const mickey_state *st) { return st ? st->bits : 0; }
 
+uint64_t mickey_instance_bits(const mickey_state *st, size_t instance)
+{
+    if (!st || instance >= st->n) {
+        fail(MICKEY_EINVAL, "mickey_instance_bits: NULL state or instance out of range");
+        return UINT64_MAX;
+    }
+    ok();
+    return instance_bits(st, instance);
+}
+
 size_t mickey_plane_pitch(size_t n) { return pad64(n) / 8; }
 
 int mickey_state_export(const mickey_state *st, uint8_t *packed, uint64_t *bits_generated)
 {
     if (!st || !packed) return fail(MICKEY_EINVAL, "mickey_state_export: NULL argument");
-    hipLaunchKernelGGL(export_kernel, dim3((unsigned)((st->n + 255) / 256)), dim3(256), 0, st->stream, st->planes,
+    if (st->poisoned && !st->snap_valid)
+        return fail(MICKEY_EDEVICE, "mickey_state_export: the state was lost to an earlier device failure");
+    // a poisoned state exports the registers saved before the call that failed
+    const uint32_t *regs = st->poisoned ? st->snap : st->planes;
+    int rc = launch_guard("export_kernel");
+    if (rc != MICKEY_OK) return rc;
+    hipLaunchKernelGGL(export_kernel, dim3((unsigned)((st->n + 255) / 256)), dim3(256), 0, st->stream, regs,
                        (uint32_t)st->nslices, (uint32_t)st->n, packed);
-    int rc = check_launch("export_kernel");
+    rc = check_launch("export_kernel");
     if (rc != MICKEY_OK) return rc;
     if (bits_generated) *bits_generated = st->bits;
     return ok();
@@ -845,11 +973,93 @@ int mickey_state_import(mickey_state *st, const uint8_t *packed, uint64_t bits_g
     if (!st || !packed) return fail(MICKEY_EINVAL, "mickey_state_import: NULL argument");
     if (bits_generated > MICKEY_MAX_BITS_PER_IV)
         return fail(MICKEY_ERANGE, "mickey_state_import: bit counter beyond 2^40");
+    int rc = launch_guard("import_kernel");
+    if (rc != MICKEY_OK) return rc;
     hipLaunchKernelGGL(import_kernel, dim3((unsigned)(st->n_pad / 256 + (st->n_pad % 256 ? 1 : 0))), dim3(256), 0,
                        st->stream, packed, (uint32_t)st->n, (uint32_t)st->nslices, st->planes);
-    int rc = check_launch("import_kernel");
+    rc = check_launch("import_kernel");
     if (rc != MICKEY_OK) return rc;
     st->bits = bits_generated;
+    st->extra.clear();
+    st->max_extra = 0;
+    st->poisoned = false;
+    st->snap_valid = false;
+    return ok();
+}
+
+size_t mickey_state_host_bytes(const mickey_state *st) { return st ? host_state_bytes(st->n) : 0; }
+
+int mickey_state_export_host(const mickey_state *st, void *host, size_t cap)
+{
+    if (!st || !host) return fail(MICKEY_EINVAL, "mickey_state_export_host: NULL argument");
+    const size_t need = host_state_bytes(st->n);
+    if (cap < need) return fail(MICKEY_EINVAL, "mickey_state_export_host: %zu bytes given, %zu needed", cap, need);
+    mickey_state *w = const_cast<mickey_state *>(st);  // scratch only; the registers are read
+    int rc = ensure_scratch(w, st->n * 25);
+    if (rc != MICKEY_OK) return rc;
+    uint8_t *packed = (uint8_t *)w->bmem;
+    uint64_t bits = 0;
+    rc = mickey_state_export(st, packed, &bits);
+    if (rc != MICKEY_OK) return rc;
+    HostHeader h;
+    memcpy(h.magic, kHostMagic, 8);
+    h.version = kHostVersion;
+    h.state_bytes = 25;
+    h.n = st->n;
+    h.reserved = 0;
+    char *p = (char *)host;
+    memcpy(p, &h, sizeof h);
+    if (hipMemcpyAsync(p + sizeof h, packed, st->n * 25, hipMemcpyDeviceToHost, st->stream) != hipSuccess ||
+        hipStreamSynchronize(st->stream) != hipSuccess)
+        return check_launch("mickey_state_export_host: copy to the host");
+    uint8_t *cnt = (uint8_t *)p + sizeof h + st->n * 25;
+    for (size_t i = 0; i < st->n; i++) {
+        const uint64_t v = instance_bits(st, i);
+        memcpy(cnt + 8 * i, &v, 8);
+    }
+    return ok();
+}
+
+int mickey_state_import_host(mickey_state *st, const void *host, size_t len)
+{
+    if (!st || !host) return fail(MICKEY_EINVAL, "mickey_state_import_host: NULL argument");
+    const size_t need = host_state_bytes(st->n);
+    HostHeader h;
+    if (len < sizeof h) return fail(MICKEY_EINVAL, "mickey_state_import_host: %zu bytes is too short", len);
+    memcpy(&h, host, sizeof h);
+    if (memcmp(h.magic, kHostMagic, 8) != 0 || h.version != kHostVersion || h.state_bytes != 25)
+        return fail(MICKEY_EINVAL, "mickey_state_import_host: not a MICKEY 2.0 state of this library");
+    if (h.n != st->n)
+        return fail(MICKEY_EINVAL, "mickey_state_import_host: %llu instances, the state has %zu",
+                    (unsigned long long)h.n, st->n);
+    if (len != need) return fail(MICKEY_EINVAL, "mickey_state_import_host: %zu bytes, expected %zu", len, need);
+    const uint8_t *cnt = (const uint8_t *)host + sizeof h + st->n * 25;
+    uint64_t lo = UINT64_MAX, hi = 0;
+    for (size_t i = 0; i < st->n; i++) {
+        uint64_t v;
+        memcpy(&v, cnt + 8 * i, 8);
+        if (v > MICKEY_MAX_BITS_PER_IV) return fail(MICKEY_ERANGE, "mickey_state_import_host: counter beyond 2^40");
+        lo = v < lo ? v : lo;
+        hi = v > hi ? v : hi;
+    }
+    int rc = ensure_scratch(st, st->n * 25);
+    if (rc != MICKEY_OK) return rc;
+    uint8_t *packed = (uint8_t *)st->bmem;
+    if (hipMemcpyAsync(packed, (const uint8_t *)host + sizeof h, st->n * 25, hipMemcpyHostToDevice, st->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(st->stream) != hipSuccess)
+        return check_launch("mickey_state_import_host: copy to the device");
+    rc = mickey_state_import(st, packed, lo);
+    if (rc != MICKEY_OK) return rc;
+    if (hi > lo) {
+        st->extra.assign(st->n, 0);
+        for (size_t i = 0; i < st->n; i++) {
+            uint64_t v;
+            memcpy(&v, cnt + 8 * i, 8);
+            st->extra[i] = v - lo;
+        }
+        st->max_extra = hi - lo;
+    }
     return ok();
 }
 
@@ -857,7 +1067,18 @@ int mickey_sync(mickey_state *st)
 {
     if (!st) return fail(MICKEY_EINVAL, "mickey_sync: NULL state");
     hipError_t e = hipStreamSynchronize(st->stream);
-    if (e != hipSuccess) return fail(MICKEY_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    if (e == hipSuccess && st->side) e = hipStreamSynchronize(st->side);
+    if (e != hipSuccess) {
+        st->poisoned = true;
+        return fail(MICKEY_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
+    return ok();
+}
+
+int mickey_debug_fail_launch(int k)
+{
+    if (k < 0) return fail(MICKEY_EINVAL, "mickey_debug_fail_launch: k must be >= 0");
+    g_fail_in.store(k);
     return ok();
 }
 

@@ -27,6 +27,7 @@
 #include "arena.h"
 #include "mickey_device.h"
 #include "mickey_host.h"
+#include "mickey_pack.h"
 #include "mickey_wordpar.h"
 
 #include <hip/hip_runtime.h>
@@ -82,82 +83,6 @@ __global__ __launch_bounds__(256) void admit_kernel(const Admit *__restrict__ ad
     lane_left[a.lane] = a.words;
     lane_sid[a.lane] = a.sid;
     atomicOr(fresh + (a.lane >> 5), 1u << (a.lane & 31u));
-}
-
-// Replace bit l of state words J0..J1-1 (0..99: r_j, 100..199: s_{j-100}) with the
-// packed state at src (25 bytes, r_0..r_99 then s_0..s_99, most significant bit first).
-template <int J0 = 0, int J1 = 200>
-__device__ __forceinline__ void gather_lane(Regs<1> &x, uint32_t l, const uint8_t *src)
-{
-    uint32_t w[7];
-#pragma unroll
-    for (int k = 0; k < 7; k++) {
-        uint32_t v = 0;
-#pragma unroll
-        for (int b = 0; b < 4; b++) {
-            const int byte = 4 * k + b;
-            const bool used = byte < 25 && byte * 8 + 7 >= J0 && byte * 8 < J1;
-            v = (v << 8) | (used ? (uint32_t)src[byte] : 0u);
-        }
-        w[k] = v;
-    }
-    const uint32_t m = 1u << l;
-    constexpr int kSel = (TA & ~TB & 0xFF) | (TC & TB);  // b ? c : a
-#pragma unroll
-    for (int j = J0; j < J1; j++) {
-        const uint32_t bit = 0u - ((w[j >> 5] >> (31 - (j & 31))) & 1u);
-        Word<1> &dst = j < 100 ? x.r[j] : x.s[j - 100];
-        dst.w[0] = __builtin_amdgcn_bitop3_b32(dst.w[0], m, bit, kSel);
-    }
-}
-
-// Pack bit l of the 200 state words into 25 bytes at dst (MSB first).
-__device__ __forceinline__ void write_back_lane(const Regs<1> &x, uint32_t l, uint8_t *dst)
-{
-    uint32_t w[7];
-#pragma unroll
-    for (int k = 0; k < 7; k++) w[k] = 0u;
-#pragma unroll
-    for (int j = 0; j < 200; j++) {
-        const uint32_t v = j < 100 ? x.r[j].w[0] : x.s[j - 100].w[0];
-        w[j >> 5] |= ((v >> l) & 1u) << (31 - (j & 31));
-    }
-#pragma unroll
-    for (int b = 0; b < 25; b++) dst[b] = (uint8_t)(w[b >> 2] >> (24 - 8 * (b & 3)));
-}
-
-// Bits J0..J1-1 of write_back_lane (0..99: r_j, 100..199: s_{j-100}), for the split
-// schedules where each wave holds part of the registers.  Bytes wholly inside the range
-// are stored; a byte shared with another part (at most one at each end) is updated with
-// two atomics on its aligned word that touch only this part's bits (the other waves and
-// the neighbouring states own the rest).
-template <int J0, int J1>
-__device__ __forceinline__ void write_back_range(const Regs<1> &x, uint32_t l, uint8_t *dst)
-{
-    uint32_t w[7];
-#pragma unroll
-    for (int k = 0; k < 7; k++) w[k] = 0u;
-#pragma unroll
-    for (int j = J0; j < J1; j++) {
-        const uint32_t v = j < 100 ? x.r[j].w[0] : x.s[j - 100].w[0];
-        w[j >> 5] |= ((v >> l) & 1u) << (31 - (j & 31));
-    }
-#pragma unroll
-    for (int b = J0 / 8; b < (J1 + 7) / 8; b++) {
-        const uint32_t v = (w[b >> 2] >> (24 - 8 * (b & 3))) & 0xFFu;
-        const int lo = 8 * b > J0 ? 8 * b : J0, hi = 8 * b + 8 < J1 ? 8 * b + 8 : J1;
-        if (lo == 8 * b && hi == 8 * b + 8) {
-            dst[b] = (uint8_t)v;
-        } else {
-            uint32_t mask = 0;
-            for (int j = lo; j < hi; j++) mask |= 1u << (7 - (j - 8 * b));
-            const uintptr_t a = (uintptr_t)(dst + b);
-            uint32_t *word = (uint32_t *)(a & ~(uintptr_t)3);
-            const uint32_t sh = (uint32_t)(a & 3u) * 8u;
-            atomicAnd(word, ~(mask << sh));
-            atomicOr(word, (v & mask) << sh);
-        }
-    }
 }
 
 // One quantum of nblocks*32 clocks on every slice with an occupied lane bit.  Each lane's
@@ -287,41 +212,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 
 constexpr uint32_t kLatStreams = 16384;  // latency stream capacity of a server
 
-// Word q of R and S from the packed state (25 bytes, r_0..r_99 s_0..s_99, MSB first).
-__device__ __forceinline__ void quad_gather(const uint8_t *src, uint32_t q, uint32_t &r, uint32_t &s)
-{
-    r = 0u;
-    s = 0u;
-    for (uint32_t b = 0; b < 32u; b++) {
-        const uint32_t i = 32u * q + b;
-        if (i >= 100u) break;
-        const uint32_t js = 100u + i;
-        r |= ((uint32_t)(src[i >> 3] >> (7u - (i & 7u))) & 1u) << b;
-        s |= ((uint32_t)(src[js >> 3] >> (7u - (js & 7u))) & 1u) << b;
-    }
-}
-
-// Lane 0 of the quad packs the quad's words into 25 bytes at dst (all four lanes call it).
-__device__ __forceinline__ void quad_write_back(uint32_t r, uint32_t s, uint32_t q, uint8_t *dst)
-{
-    const uint32_t rw[4] = {qperm<qp(0, 0, 0, 0)>(r), qperm<qp(1, 1, 1, 1)>(r), qperm<qp(2, 2, 2, 2)>(r),
-                            qperm<qp(3, 3, 3, 3)>(r)};
-    const uint32_t sw[4] = {qperm<qp(0, 0, 0, 0)>(s), qperm<qp(1, 1, 1, 1)>(s), qperm<qp(2, 2, 2, 2)>(s),
-                            qperm<qp(3, 3, 3, 3)>(s)};
-    if (q) return;
-#pragma unroll
-    for (int byte = 0; byte < 25; byte++) {
-        uint32_t v = 0;
-#pragma unroll
-        for (int k = 0; k < 8; k++) {
-            const int j = 8 * byte + k;
-            const uint32_t bit = j < 100 ? (rw[j >> 5] >> (j & 31)) & 1u : (sw[(j - 100) >> 5] >> ((j - 100) & 31)) & 1u;
-            v |= bit << (7 - k);
-        }
-        dst[byte] = (uint8_t)v;
-    }
-}
-
 // One quantum of the latency streams: every busy stream runs up to nwords x 32 clocks,
 // storing one output word per 32 clocks (lane 0), then keeps its words in lat_state; a
 // stream whose words end packs its state back into the pool and joins the completion
@@ -379,6 +269,7 @@ struct Request {
     uint64_t next_same = ~0ull;  // next request waiting on the same state
     uint64_t words_admitted = 0, words_done = 0;
     uint32_t cur_words = 0;    // words of the admission in flight
+    uint64_t lat_words = 0;    // words admitted to latency streams
     bool refused = false;      // passed 2^40 bits
     bool done = false;
     bool released = false;
@@ -1046,6 +937,7 @@ bool admit_next(mickey_server *s, Request &r, uint64_t t_admit)
     if (lat) {
         s->lat_free.pop_back();
         s->lat_busy++;
+        r.lat_words += words;
     } else {
         s->free_lanes.pop_back();
     }
@@ -1425,6 +1317,18 @@ int mickey_server_times_many(const mickey_server *s, const uint64_t *ids, size_t
 }
 
 // Completed request ids since the last call (up to cap); returns how many were written.
+int mickey_server_latency_words_many(const mickey_server *s, const uint64_t *ids, size_t n, uint64_t *out)
+{
+    if (!s || (n && (!ids || !out))) return fail(MICKEY_EINVAL, "mickey_server_latency_words_many: bad argument");
+    for (size_t k = 0; k < n; k++) {
+        if (ids[k] >= s->reqs.size())
+            return fail(MICKEY_EINVAL, "mickey_server_latency_words_many: no request %llu",
+                        (unsigned long long)ids[k]);
+        out[k] = s->reqs[ids[k]].lat_words;
+    }
+    return ok();
+}
+
 int64_t mickey_server_poll(mickey_server *s, uint64_t *ids, size_t cap)
 {
     if (!s || (!ids && cap)) return fail(MICKEY_EINVAL, "mickey_server_poll: bad argument");

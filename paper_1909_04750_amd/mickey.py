@@ -21,6 +21,8 @@ EXPORTED = [
     "mickey_free", "mickey_set_stream", "mickey_set_word_bits", "mickey_set_schedule", "mickey_set_transpose", "mickey_num_instances",
     "mickey_bits_generated", "mickey_plane_pitch", "mickey_state_export", "mickey_state_import",
     "mickey_sync", "mickey_last_error", "mickey_last_error_message", "mickey_ops_per_clock",
+    "mickey_generate_batch", "mickey_instance_bits", "mickey_state_host_bytes", "mickey_state_export_host",
+    "mickey_state_import_host", "mickey_debug_fail_launch",
     "mickey_batch_create", "mickey_batch_set", "mickey_batch_run", "mickey_batch_sync", "mickey_batch_stream",
     "mickey_batch_set_params", "mickey_batch_get_params", "mickey_batch_autotune", "mickey_batch_free",
     "mickey_batch_set_latency_threshold", "mickey_batch_get_routing",
@@ -28,6 +30,7 @@ EXPORTED = [
     "mickey_server_result", "mickey_server_copy", "mickey_server_release", "mickey_server_stats",
     "mickey_server_state", "mickey_server_stream", "mickey_server_free", "mickey_server_submit_many",
     "mickey_server_release_many", "mickey_server_times_many", "mickey_server_wait",
+    "mickey_server_latency_words_many",
     "mickey_server_set_chunk", "mickey_server_poll_chunks", "mickey_server_release_chunks",
     "mickey_server_copy_chunk", "mickey_server_set_kernel", "mickey_server_set_latency",
     "grain_init", "grain_rekey", "grain_generate", "grain_generate_rowmajor", "grain_free", "grain_set_stream",
@@ -95,6 +98,18 @@ def load_library():
     L.mickey_last_error_message.restype = ctypes.c_char_p
     L.mickey_ops_per_clock.argtypes = []
     L.mickey_ops_per_clock.restype = i
+    L.mickey_generate_batch.argtypes = [vp, vp, sz]
+    L.mickey_generate_batch.restype = i
+    L.mickey_instance_bits.argtypes = [vp, sz]
+    L.mickey_instance_bits.restype = u64
+    L.mickey_state_host_bytes.argtypes = [vp]
+    L.mickey_state_host_bytes.restype = sz
+    L.mickey_state_export_host.argtypes = [vp, vp, sz]
+    L.mickey_state_export_host.restype = i
+    L.mickey_state_import_host.argtypes = [vp, vp, sz]
+    L.mickey_state_import_host.restype = i
+    L.mickey_debug_fail_launch.argtypes = [i]
+    L.mickey_debug_fail_launch.restype = i
     L.mickey_batch_create.argtypes = [sz, vp]
     L.mickey_batch_create.restype = vp
     L.mickey_batch_set.argtypes = [vp, vp, vp, vp, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_void_p), sz]
@@ -144,6 +159,8 @@ def load_library():
     L.mickey_server_release_many.restype = i
     L.mickey_server_times_many.argtypes = [vp, vp, sz, vp]
     L.mickey_server_times_many.restype = i
+    L.mickey_server_latency_words_many.argtypes = [vp, vp, sz, vp]
+    L.mickey_server_latency_words_many.restype = i
     L.mickey_server_wait.argtypes = [vp]
     L.mickey_server_wait.restype = i
     L.mickey_server_set_latency.argtypes = [vp, ctypes.c_uint32, u64, u64]
@@ -222,6 +239,15 @@ def plane_pitch(n: int) -> int:
 
 def ops_per_clock() -> int:
     return int(load_library().mickey_ops_per_clock())
+
+
+def debug_fail_launch(k: int) -> None:
+    """Make the k-th launch from now fail as if the device had refused it (0 cancels)."""
+    _check(load_library().mickey_debug_fail_launch(int(k)))
+
+
+# mickey_req: instance, nbits, out (device address), layout, and the struct's tail padding
+REQ_DTYPE = [("instance", "<u8"), ("nbits", "<u8"), ("out", "<u8"), ("layout", "<i4"), ("pad", "<i4")]
 
 
 def _dev_ptr(t, name: str, nbytes: int):
@@ -320,7 +346,46 @@ class Mickey:
         _check(load_library().mickey_generate_rowmajor(self._h, nbits, pu, pf))
         return out_u32, out_f32
 
+    def generate_batch(self, instances, nbits, outs, layouts=ROWMAJOR_U32) -> None:
+        """Per-instance requests (mickey_generate_batch): request k resumes instance
+        instances[k] for nbits[k] bits into outs[k] (a CUDA tensor of nbits[k]/32 words, or
+        a device address), with layouts[k] ROWMAJOR_U32 or ROWMAJOR_F32 (one value for all)."""
+        import numpy as np
+        n = len(instances)
+        req = np.zeros(n, dtype=REQ_DTYPE)
+        req["instance"] = np.asarray(instances, dtype=np.uint64)
+        req["nbits"] = np.asarray(nbits, dtype=np.uint64)
+        req["layout"] = np.broadcast_to(np.asarray(layouts, dtype=np.int32), (n,))
+        ptrs = []
+        for k, o in enumerate(outs):
+            if isinstance(o, int):
+                ptrs.append(o)
+            else:
+                ptrs.append(_dev_ptr(o, "outs[%d]" % k, int(req["nbits"][k]) // 8).value or 0)
+        req["out"] = np.asarray(ptrs, dtype=np.uint64)
+        _check(load_library().mickey_generate_batch(self._h, req.ctypes.data, n))
+
+    def instance_bits(self, i: int) -> int:
+        v = int(load_library().mickey_instance_bits(self._h, int(i)))
+        if v == (1 << 64) - 1:
+            _check(load_library().mickey_last_error())
+        return v
+
     # -- state
+    def export_host(self) -> bytes:
+        """The state in host form (mickey_state_export_host): header, packed registers,
+        per-instance bit counters."""
+        import numpy as np
+        L = load_library()
+        buf = np.zeros(int(L.mickey_state_host_bytes(self._h)), dtype=np.uint8)
+        _check(L.mickey_state_export_host(self._h, buf.ctypes.data, buf.nbytes))
+        return buf.tobytes()
+
+    def import_host(self, blob: bytes) -> None:
+        import numpy as np
+        a = np.frombuffer(bytes(blob), dtype=np.uint8)
+        _check(load_library().mickey_state_import_host(self._h, a.ctypes.data, a.nbytes))
+
     def export_state(self, out=None):
         import torch
         if out is None:
@@ -482,6 +547,14 @@ class Server:
         a = np.ascontiguousarray(ids, dtype=np.uint64)
         out = np.zeros((len(a), 3), dtype=np.uint64)
         _check(load_library().mickey_server_times_many(self._h, a.ctypes.data, len(a), out.ctypes.data))
+        return out
+
+    def latency_words_many(self, ids):
+        """Words of each request admitted to latency streams so far."""
+        import numpy as np
+        a = np.ascontiguousarray(ids, dtype=np.uint64)
+        out = np.zeros(len(a), dtype=np.uint64)
+        _check(load_library().mickey_server_latency_words_many(self._h, a.ctypes.data, len(a), out.ctypes.data))
         return out
 
     def step(self) -> None:

@@ -98,3 +98,30 @@ def test_headline_kernel_code_hash_is_found():
     h2 = codeobj.kernel_code_hash(LIB_PATH, "_ZN12_GLOBAL__N_120gen_bitsliced_kernelILi2EEEvPjjjmS1_")
     assert h1 and h2 and h1 != h2 and len(h1) == 16
     assert codeobj.kernel_code_hash(LIB_PATH, "no_such_kernel") is None
+
+
+def test_request_record_layout_matches_binding(tmp_path):
+    """mickey_req as the binding builds it (numpy structured array)."""
+    import numpy as np
+    import subprocess
+    src = tmp_path / "req.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "mickey.h"\n'
+                   "int main(void){printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(mickey_req),"
+                   " offsetof(mickey_req, instance), offsetof(mickey_req, nbits), offsetof(mickey_req, out),"
+                   " offsetof(mickey_req, layout));return 0;}\n")
+    exe = tmp_path / "req"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    dt = np.dtype(mickey.REQ_DTYPE)
+    assert got == [dt.itemsize] + [dt.fields[f][1] for f in ("instance", "nbits", "out", "layout")]
+
+
+def test_new_entry_points_validate_without_gpu(lib):
+    assert lib.mickey_debug_fail_launch(-1) == mickey.EINVAL
+    assert lib.mickey_debug_fail_launch(0) == mickey.OK
+    assert lib.mickey_instance_bits(None, 0) == (1 << 64) - 1
+    assert lib.mickey_last_error() == mickey.EINVAL
+    assert lib.mickey_state_host_bytes(None) == 0
+    assert lib.mickey_state_export_host(None, None, 0) == mickey.EINVAL
+    assert lib.mickey_state_import_host(None, None, 0) == mickey.EINVAL
+    assert lib.mickey_generate_batch(None, None, 0) == mickey.EINVAL

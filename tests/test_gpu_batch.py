@@ -208,3 +208,31 @@ def test_latency_mode_matches_bitsliced_and_oracle():
     want = np.concatenate(oracle_words(keys, ivs, ivb, nbits))
     assert (outs[1][: len(want)] == want).all()
     b.close()
+
+
+def test_batch_10k_full_lengths_sampled_parity():
+    """The batched workload at its configured lengths (seed 4: 10,000 requests, log-uniform
+    up to 2^24 bits, IV lengths 0..80), one launch with size-aware routing: the 8 longest
+    requests (latency mode) and 24 seeded others against the oracle, full length."""
+    keys, ivs, ivb, nbits = synth.batch_requests(4, 10000)
+    arena, offs, ptrs = arena_for(nbits)
+    b = mickey.Batch(len(nbits))
+    b.set(to_dev(keys), to_dev(ivs), to_dev(ivb), nbits, ptrs)
+    b.run()
+    b.sync()
+    threshold, nlat, _ = b.routing()
+    b.close()
+    order = np.argsort(-nbits.astype(np.int64), kind="stable")
+    rng = np.random.default_rng(9)
+    pick = np.concatenate([order[:8], rng.choice(order[8:], 24, replace=False)])
+    assert nlat > 0 and all(int(nbits[i]) >= threshold for i in order[:8])
+    from concurrent.futures import ThreadPoolExecutor
+
+    def want(i):  # one instance per job: ctypes releases the GIL while the oracle runs
+        return oracle.generate_many(keys[i:i + 1], ivs[i:i + 1], ivb[i:i + 1], int(nbits[i]))[0].tobytes()
+    with ThreadPoolExecutor(8) as pool:
+        wants = list(pool.map(want, pick))
+    for i, wb in zip(pick, wants):
+        w = int(nbits[i]) // 32
+        got = arena[int(offs[i]):int(offs[i]) + w].cpu().numpy().view(np.uint32)
+        assert got.astype(">u4").tobytes() == wb, (int(i), int(nbits[i]))
