@@ -109,6 +109,18 @@ int mickey_generate(mickey_state *st, uint64_t nbits, void *out, int layout);
  * and MICKEY_ROWMAJOR_F32.  nbits % 32 == 0. */
 int mickey_generate_rowmajor(mickey_state *st, uint64_t nbits, uint32_t *out_u32, float *out_f32);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops or harnesses that forbid hipMalloc): mickey_generate_rowmajor with the same
+ * arguments, results and errors, that allocates nothing.  The staged transposition's
+ * register snapshot and bit-plane chunks live in a library-owned static device array of
+ * 256 MiB, which every device that runs the library holds until the process ends; chunks
+ * are as many clocks as fit beside the snapshot (at most 8192), and everything runs on the
+ * state's stream.  States of more than ~8.1 million instances (200 + 64 planes exceeding
+ * the array) get MICKEY_EINVAL.  All calls on one device share the array: calls that
+ * overlap on a device (different streams or host threads) race and must be serialised by
+ * the caller. */
+int mickey_generate_rowmajor_noalloc(mickey_state *st, uint64_t nbits, uint32_t *out_u32, float *out_f32);
+
 /* Per-instance requests (the paper's problem statement, Sec. IV-D: independent instances,
  * each with its own key and IV).  Request k resumes instance reqs[k].instance of `st` for
  * reqs[k].nbits keystream bits (a multiple of 32; 0 is allowed and does nothing) and writes

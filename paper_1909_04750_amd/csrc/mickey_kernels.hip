@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -411,6 +412,14 @@ __global__ __launch_bounds__(256) void import_kernel(const uint8_t *__restrict__
 
 // ------------------------------------------------------------------------ C ABI
 
+// Scratch of the allocation-free entry point (mickey_generate_rowmajor_noalloc): the staged
+// path's register snapshot and its two bit-plane chunk buffers.  Every device that runs the
+// library holds one copy until the process ends; nothing in it has to start at zero (each
+// call writes what it later reads).  Host code reaches it only through the per-device
+// address from hipGetSymbolAddress, never through the array's name.
+constexpr size_t kNoAllocScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) uint32_t scratch[kNoAllocScratchBytes / 4];
+
 namespace mickey_host {
 
 thread_local int g_err = MICKEY_OK;
@@ -445,6 +454,29 @@ void prefix_error(const char *prefix)
     char msg[sizeof g_msg];
     memcpy(msg, g_msg, sizeof msg);
     snprintf(g_msg, sizeof g_msg, "%s: %s", prefix, msg);
+}
+
+// Device address of `scratch` on each device, taken once per device with that device
+// current (the first mickey_init on it).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_addr[kMaxDevices] = {};
+
+int scratch_address(int device, uint32_t **addr)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(MICKEY_EDEVICE, "device %d out of range", device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(MICKEY_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        }
+        g_scratch_addr[device] = (uint32_t *)p;
+    }
+    *addr = g_scratch_addr[device];
+    return MICKEY_OK;
 }
 
 // Launches left before an injected failure (0: none pending); see mickey_debug_fail_launch.
@@ -610,6 +642,7 @@ mickey_state *init_impl(const uint8_t *keys, const uint8_t *ivs, const uint8_t *
         return nullptr;
     }
     int rc = run_init(st, keys, ivs, iv_bits);
+    if (rc == MICKEY_OK) rc = scratch_address(st->device, &st->noalloc);
     if (rc != MICKEY_OK) {
         destroy(st);
         prefix_error("mickey_init");
@@ -669,19 +702,22 @@ int launch_generate_planes(mickey_state *st, uint64_t nbits, uint32_t *out);
 // The registers are first copied to `snap` (200 planes): if a launch after the first
 // generate fails, they are copied back, so the call fails with the state unchanged; if
 // even that copy cannot be enqueued, the state is poisoned.
-//   chunk: two buffers of chunk_clocks planes each (chunk_clocks a multiple of 1024)
+//   chunk: two buffers of chunk_clocks planes each (chunk_clocks a multiple of 32)
+//   overlap: transposes may run on the side stream (else everything stays on the state's
+//            stream, in order, with no event)
 int generate_staged_with(mickey_state *st, uint64_t nbits, uint32_t *out_u32, float *out_f32, uint32_t *chunk,
-                         uint64_t chunk_clocks, uint32_t *snap)
+                         uint64_t chunk_clocks, uint32_t *snap, bool overlap)
 {
     const size_t pitch = st->nslices * 4;
-    int rc = ensure_side(st);
+    overlap = overlap && !use_split4(st);
+    int rc = overlap ? ensure_side(st) : MICKEY_OK;
     if (rc != MICKEY_OK) return rc;
     rc = launch_guard("state snapshot");
     if (rc != MICKEY_OK) return rc;
     if (hipMemcpyAsync(snap, st->planes, 200 * pitch, hipMemcpyDeviceToDevice, st->stream) != hipSuccess)
         return check_launch("state snapshot");
     const uint64_t nwords = nbits / 32;
-    hipStream_t tp_stream = use_split4(st) ? st->stream : st->side;
+    hipStream_t tp_stream = overlap ? st->side : st->stream;
     int last = 0;
     uint64_t k = 0;
     bool changed = false;  // a generate kernel has been launched on the registers
@@ -689,15 +725,15 @@ int generate_staged_with(mickey_state *st, uint64_t nbits, uint32_t *out_u32, fl
         const int b = (int)(k & 1);
         uint32_t *buf = chunk + (size_t)b * chunk_clocks * st->nslices;
         const uint64_t nc = nbits - c0 < chunk_clocks ? nbits - c0 : chunk_clocks;
-        if (k >= 2 && hipStreamWaitEvent(st->stream, st->ev_tp[b], 0) != hipSuccess) {
+        if (overlap && k >= 2 && hipStreamWaitEvent(st->stream, st->ev_tp[b], 0) != hipSuccess) {
             rc = check_launch("hipStreamWaitEvent");
             break;
         }
         rc = launch_generate_planes(st, nc, buf);
         if (rc != MICKEY_OK) break;
         changed = true;
-        if (hipEventRecord(st->ev_gen[b], st->stream) != hipSuccess ||
-            hipStreamWaitEvent(tp_stream, st->ev_gen[b], 0) != hipSuccess) {
+        if (overlap && (hipEventRecord(st->ev_gen[b], st->stream) != hipSuccess ||
+                        hipStreamWaitEvent(tp_stream, st->ev_gen[b], 0) != hipSuccess)) {
             rc = check_launch("hipEventRecord");
             break;
         }
@@ -709,13 +745,13 @@ int generate_staged_with(mickey_state *st, uint64_t nbits, uint32_t *out_u32, fl
                            (uint32_t)nc, (uint32_t)st->n, nwords, c0 / 32, out_u32, out_f32);
         rc = check_launch("rowmajor_transpose_kernel");
         if (rc != MICKEY_OK) break;
-        if (hipEventRecord(st->ev_tp[b], tp_stream) != hipSuccess) {
+        if (overlap && hipEventRecord(st->ev_tp[b], tp_stream) != hipSuccess) {
             rc = check_launch("hipEventRecord");
             break;
         }
         last = b;
     }
-    if (rc == MICKEY_OK && hipStreamWaitEvent(st->stream, st->ev_tp[last], 0) != hipSuccess)
+    if (overlap && rc == MICKEY_OK && hipStreamWaitEvent(st->stream, st->ev_tp[last], 0) != hipSuccess)
         rc = check_launch("hipStreamWaitEvent");
     if (rc != MICKEY_OK && changed) {
         // the generate kernels all ran on the state's stream: the copy back follows them
@@ -754,7 +790,7 @@ int generate_staged(mickey_state *st, uint64_t nbits, uint32_t *out_u32, float *
         st->snap = nullptr;
         return fail(MICKEY_ENOMEM, "mickey_generate: cannot allocate the %zu-byte state snapshot", 200 * pitch);
     }
-    return generate_staged_with(st, nbits, out_u32, out_f32, st->chunk, st->chunk_clocks, st->snap);
+    return generate_staged_with(st, nbits, out_u32, out_f32, st->chunk, st->chunk_clocks, st->snap, true);
 }
 
 // nbits clocks of every instance as bit-planes (pitch nslices*4 bytes) to out.
@@ -881,6 +917,27 @@ int mickey_generate(mickey_state *st, uint64_t nbits, void *out, int layout)
 int mickey_generate_rowmajor(mickey_state *st, uint64_t nbits, uint32_t *out_u32, float *out_f32)
 {
     return generate_impl(st, nbits, MICKEY_ROWMAJOR_U32, nullptr, out_u32, out_f32);
+}
+
+int mickey_generate_rowmajor_noalloc(mickey_state *st, uint64_t nbits, uint32_t *out_u32, float *out_f32)
+{
+    int rc = check_generate(st, nbits, MICKEY_ROWMAJOR_U32);
+    if (rc != MICKEY_OK) return rc;
+    if (!out_u32 && !out_f32) return fail(MICKEY_EINVAL, "mickey_generate_rowmajor_noalloc: NULL output");
+    const size_t pitch = st->nslices * 4;
+    const size_t snap_bytes = (200 * pitch + 255) / 256 * 256;
+    if (snap_bytes + 2 * 32 * pitch > kNoAllocScratchBytes)
+        return fail(MICKEY_EINVAL, "mickey_generate_rowmajor_noalloc: %zu instances exceed the %zu MiB scratch "
+                    "(at most %zu)", st->n, kNoAllocScratchBytes >> 20, kNoAllocScratchBytes / 264 / 4 * 32);
+    uint64_t cc = (kNoAllocScratchBytes - snap_bytes) / (2 * pitch);
+    cc = cc >= (uint64_t)kTpClocks ? cc / kTpClocks * kTpClocks : cc / 32 * 32;
+    if (cc > 8192) cc = 8192;
+    uint32_t *snap = st->noalloc;
+    rc = generate_staged_with(st, nbits, out_u32, out_f32, st->noalloc + snap_bytes / 4, cc, snap, false);
+    if (rc != MICKEY_OK) return rc;
+    st->bits += nbits;
+    st->snap_valid = false;
+    return ok();
 }
 
 int mickey_rekey(mickey_state *st, const uint8_t *keys, const uint8_t *ivs, const uint8_t *iv_bits)

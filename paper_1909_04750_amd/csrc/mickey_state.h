@@ -32,6 +32,7 @@ struct mickey_state {
                                 // several state-changing launches (restored if one fails)
     bool snap_valid = false;    // snap holds the registers of the last good state
     bool poisoned = false;      // a failure left the registers unknown (MICKEY_EDEVICE from now on)
+    uint32_t *noalloc = nullptr;  // device address of this device's static scratch array
     hipStream_t side = nullptr;  // staged transposes and latency-mode requests run here
     hipEvent_t ev_gen[2] = {nullptr, nullptr}, ev_tp[2] = {nullptr, nullptr};
     // mickey_generate_batch: device scratch (metadata, packed states) and the pinned host

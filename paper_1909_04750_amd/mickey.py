@@ -22,7 +22,7 @@ EXPORTED = [
     "mickey_bits_generated", "mickey_plane_pitch", "mickey_state_export", "mickey_state_import",
     "mickey_sync", "mickey_last_error", "mickey_last_error_message", "mickey_ops_per_clock",
     "mickey_generate_batch", "mickey_instance_bits", "mickey_state_host_bytes", "mickey_state_export_host",
-    "mickey_state_import_host", "mickey_debug_fail_launch",
+    "mickey_state_import_host", "mickey_debug_fail_launch", "mickey_generate_rowmajor_noalloc",
     "mickey_batch_create", "mickey_batch_set", "mickey_batch_run", "mickey_batch_sync", "mickey_batch_stream",
     "mickey_batch_set_params", "mickey_batch_get_params", "mickey_batch_autotune", "mickey_batch_free",
     "mickey_batch_set_latency_threshold", "mickey_batch_get_routing",
@@ -98,6 +98,8 @@ def load_library():
     L.mickey_last_error_message.restype = ctypes.c_char_p
     L.mickey_ops_per_clock.argtypes = []
     L.mickey_ops_per_clock.restype = i
+    L.mickey_generate_rowmajor_noalloc.argtypes = [vp, u64, vp, vp]
+    L.mickey_generate_rowmajor_noalloc.restype = i
     L.mickey_generate_batch.argtypes = [vp, vp, sz]
     L.mickey_generate_batch.restype = i
     L.mickey_instance_bits.argtypes = [vp, sz]
