@@ -39,6 +39,8 @@ EXPORTED = [
     "aes_ctr_init", "aes_ctr_generate", "aes_ctr_generate_rowmajor", "aes_ctr_seek", "aes_ctr_free",
     "aes_ctr_set_stream", "aes_ctr_num_instances", "aes_ctr_bits_generated", "aes_ctr_plane_pitch",
     "aes_ctr_sync", "aes_ctr_ops_per_block",
+    "mickey128_init", "mickey128_generate", "mickey128_sync", "mickey128_export", "mickey128_free",
+    "mickey128_num_instances", "mickey128_bits_generated", "mickey128_plane_pitch", "mickey128_ops_per_clock",
 ]
 GRAIN_PACKED_STATE_BYTES = 20
 
@@ -225,6 +227,24 @@ def load_library():
     L.aes_ctr_sync.restype = i
     L.aes_ctr_ops_per_block.argtypes = []
     L.aes_ctr_ops_per_block.restype = i
+    L.mickey128_init.argtypes = [vp, vp, vp, sz, vp]
+    L.mickey128_init.restype = vp
+    L.mickey128_generate.argtypes = [vp, u64, vp]
+    L.mickey128_generate.restype = i
+    L.mickey128_sync.argtypes = [vp]
+    L.mickey128_sync.restype = i
+    L.mickey128_export.argtypes = [vp, vp]
+    L.mickey128_export.restype = i
+    L.mickey128_free.argtypes = [vp]
+    L.mickey128_free.restype = None
+    L.mickey128_num_instances.argtypes = [vp]
+    L.mickey128_num_instances.restype = sz
+    L.mickey128_bits_generated.argtypes = [vp]
+    L.mickey128_bits_generated.restype = u64
+    L.mickey128_plane_pitch.argtypes = [sz]
+    L.mickey128_plane_pitch.restype = sz
+    L.mickey128_ops_per_clock.argtypes = []
+    L.mickey128_ops_per_clock.restype = i
     _lib = L
     return L
 
@@ -793,6 +813,67 @@ class AesCtr:
     def close(self) -> None:
         if getattr(self, "_h", None):
             load_library().aes_ctr_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mickey128_ops_per_clock() -> int:
+    return int(load_library().mickey128_ops_per_clock())
+
+
+class Mickey128:
+    """n bitsliced MICKEY-128 2.0 instances resident on the GPU (mickey128_state): 128-bit
+    keys and IVs (n x 16 bytes, bits MSB first) and IV lengths 0..128 (n bytes, or None
+    for 128), all device tensors.  Output: bit-planes of pitch n_pad/8 bytes."""
+
+    def __init__(self, keys, ivs, iv_bits=None, stream=None):
+        n = int(keys.shape[0])
+        L = load_library()
+        pb = None if iv_bits is None else _dev_ptr(iv_bits, "iv_bits", n)
+        h = L.mickey128_init(_dev_ptr(keys, "keys", 16 * n), _dev_ptr(ivs, "ivs", 16 * n), pb, n,
+                             _stream_handle(stream))
+        if not h:
+            raise MickeyError(L.mickey_last_error(), L.mickey_last_error_message().decode())
+        self._h = ctypes.c_void_p(h)
+        self.n = n
+
+    @property
+    def bits_generated(self) -> int:
+        return int(load_library().mickey128_bits_generated(self._h))
+
+    @property
+    def pitch(self) -> int:
+        return int(load_library().mickey128_plane_pitch(self.n))
+
+    def generate(self, nbits: int, out=None):
+        import torch
+        nbits = int(nbits)
+        nbytes = nbits * self.pitch
+        if out is None:
+            out = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        _check(load_library().mickey128_generate(self._h, nbits, _dev_ptr(out, "out", nbytes)))
+        return out
+
+    def export_planes(self, out=None):
+        """The 320 register planes (r_0..r_159, s_0..s_159), pitch bytes each."""
+        import torch
+        nbytes = 320 * self.pitch
+        if out is None:
+            out = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        _check(load_library().mickey128_export(self._h, _dev_ptr(out, "planes", nbytes)))
+        return out
+
+    def sync(self) -> None:
+        _check(load_library().mickey128_sync(self._h))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load_library().mickey128_free(self._h)
             self._h = None
 
     def __del__(self):

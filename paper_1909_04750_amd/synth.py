@@ -14,6 +14,7 @@ stand in for both.
 Recipes (instance i of n):
   key  bytes = big-endian bytes of draw 4i (8 bytes) then the top 2 bytes of draw 4i+1
   IV   bytes = big-endian bytes of draw 4i+2 then the top 2 bytes of draw 4i+3
+  (128-bit keys and IVs: all 8 bytes of draws 4i, 4i+1 and of 4i+2, 4i+3)
   IV length  (mixed-length workloads only) = {0, 32, 64, 80}[draw (4n + i) >> 62]
 """
 from __future__ import annotations
@@ -75,6 +76,17 @@ def aes_inputs(seed: int, n: int, idx=None):
     key = kd.astype(">u8").view(np.uint8).reshape(16).copy()
     nonces = draws(seed, np.uint64(4) * i).astype(">u8").view(np.uint8).reshape(-1, 8).copy()
     return key, nonces
+
+
+def keys_ivs128(seed: int, n: int, idx=None):
+    """MICKEY-128 inputs: keys and IVs uint8 [k, 16], key i = draws 4i and 4i+1
+    big-endian, IV i = draws 4i+2 and 4i+3 big-endian (128 bits each)."""
+    i = np.arange(n, dtype=np.uint64) if idx is None else np.asarray(idx, dtype=np.uint64)
+    f = np.uint64(4)
+    d = [draws(seed, f * i + np.uint64(k)).astype(">u8").view(np.uint8).reshape(-1, 8) for k in range(4)]
+    keys = np.ascontiguousarray(np.concatenate(d[:2], axis=1))
+    ivs = np.ascontiguousarray(np.concatenate(d[2:], axis=1))
+    return keys, ivs
 
 
 def iv_lengths_mixed(seed: int, n: int, idx=None) -> np.ndarray:
@@ -142,6 +154,9 @@ def workload(name: str):
         "grain-4m": (6, 1 << 22, 8192, "grain"),
         # AES-128-CTR: one key, 2^22 streams with 64-bit nonces, 8192 bits (64 blocks) each
         "aes-4m": (7, 1 << 22, 8192, "aes"),
+        # MICKEY-128 2.0: 3 * 2^20 instances (three waves per SIMD), 128-bit keys and IVs,
+        # 8192 bits each (3 GiB of bitsliced output)
+        "mickey128-3m": (8, 3 << 20, 8192, "128"),
     }
     return table[name]
 

@@ -9,14 +9,14 @@ import pytest
 from paper_1909_04750_amd import build, mickey
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("mickey.h", "grain.h", "aes.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("mickey.h", "grain.h", "aes.h", "mickey128.h")]
 
 
 def declared_functions():
     names = []
     for h in HEADERS:
         text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
-        names += re.findall(r"\b((?:mickey|grain|aes_ctr)_\w+)\s*\(", text)
+        names += re.findall(r"\b((?:mickey128|mickey|grain|aes_ctr)_\w+)\s*\(", text)
     return sorted(set(names))
 
 
