@@ -298,6 +298,58 @@ __device__ __forceinline__ void s_upper(Regs<K> &x, Word<K> &prev, const Word<K>
     x.s[0] = fbs;
 }
 
+// The same S update as a descending sweep, for the split S wave: `nxt` carries the old
+// s_{I+1}.  An ascending sweep leaves the new s_i in the register of the old s_{i-1}
+// (the value that dies at that step) and a descending one in that of the old s_{i+1},
+// so alternating the two returns every word to its register every two clocks with one
+// spare register and no copies (a wave holds one register set, not two).
+template <int I, int K>
+__device__ __forceinline__ void s_step_desc(Regs<K> &x, Word<K> &nxt, const Word<K> &fbs, const Word<K> &g0,
+                                            const Word<K> &g1)
+{
+    constexpr int bb = in_set(kComp0, I) ? (TB ^ 0xFF) : TB;
+    constexpr int cc = in_set(kComp1, I) ? (TC ^ 0xFF) : TC;
+    constexpr int imm = (TA ^ (bb & cc)) & 0xFF;
+    Word<K> old = x.s[I];
+    Word<K> v = b3<imm>(x.s[I - 1], x.s[I], nxt);
+    constexpr bool f0 = in_set(kFb0, I), f1 = in_set(kFb1, I);
+    if constexpr (f0 && f1) v = v ^ fbs;
+    else if constexpr (f0) v = v ^ g0;
+    else if constexpr (f1) v = v ^ g1;
+    x.s[I] = v;
+    nxt = old;
+}
+
+template <int K, int HI, int... J>
+__device__ __forceinline__ void s_range_desc(Regs<K> &x, Word<K> &nxt, const Word<K> &fbs, const Word<K> &g0,
+                                             const Word<K> &g1, std::integer_sequence<int, J...>)
+{
+    (s_step_desc<HI - J, K>(x, nxt, fbs, g0, g1), ...);
+}
+// s_99 (from the old s_98), then s_98 .. s_{kSCut}; returns nothing, leaves the old
+// s_{kSCut} in nxt
+template <int K>
+__device__ __forceinline__ void s_upper_desc(Regs<K> &x, Word<K> &nxt, const Word<K> &fbs, const Word<K> &g0,
+                                             const Word<K> &g1)
+{
+    nxt = x.s[99];
+    Word<K> v = x.s[98];
+    constexpr bool f0 = in_set(kFb0, 99), f1 = in_set(kFb1, 99);
+    if constexpr (f0 && f1) v = v ^ fbs;
+    else if constexpr (f0) v = v ^ g0;
+    else if constexpr (f1) v = v ^ g1;
+    x.s[99] = v;
+    s_range_desc<K, 98>(x, nxt, fbs, g0, g1, std::make_integer_sequence<int, 98 - kSCut + 1>{});
+}
+// s_{kSCut-1} .. s_1, then s_0
+template <int K>
+__device__ __forceinline__ void s_lower_desc(Regs<K> &x, Word<K> &nxt, const Word<K> &fbs, const Word<K> &g0,
+                                             const Word<K> &g1)
+{
+    s_range_desc<K, kSCut - 1>(x, nxt, fbs, g0, g1, std::make_integer_sequence<int, kSCut - 1>{});
+    x.s[0] = fbs;
+}
+
 // Initialisation clock: mixing on, input word `in` (one input bit per lane).
 template <int K, bool MASKED>
 __device__ __forceinline__ void clock_mix(Regs<K> &x, const Word<K> &in, const Word<K> &m)

@@ -324,6 +324,25 @@ __device__ __forceinline__ void split_s_clock(Regs<1> &x, Word<1> &r33, SplitLds
     __builtin_amdgcn_sched_barrier(0);  // c_S of the next clock waits for r_33 only here
 }
 
+// The S wave's clock as a descending sweep (s_99..s_34 before the exchange, s_33..s_1
+// after); alternated with split_s_clock it keeps the S words in one register set.
+__device__ __forceinline__ void split_s_clock_desc(Regs<1> &x, Word<1> &r33, SplitLds &xl, uint32_t lane, int ph)
+{
+    const Word<1> cs = x.s[67] ^ r33;
+    const Word<1> fbs = x.s[99];
+    const Word<1> g1 = fbs & cs;
+    const Word<1> g0 = fbs ^ g1;
+    Word<1> nxt;
+    s_upper_desc<1>(x, nxt, fbs, g0, g1);
+    xl.s34[ph][lane] = x.s[kSCut].w[0];
+    xl.s0[ph][lane] = fbs.w[0];  // the next s_0
+    lds_barrier();
+    r33.w[0] = xl.r33[ph][lane];
+    __builtin_amdgcn_sched_barrier(0);
+    s_lower_desc<1>(x, nxt, fbs, g0, g1);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // ---------------------------------------------------------------------------------
 // Four-wave split clock (one workgroup of four waves per 64 slices): wave 0 keeps
 // r_0..r_49, wave 1 r_50..r_99, wave 2 s_0..s_49, wave 3 s_50..s_99.  Each position's

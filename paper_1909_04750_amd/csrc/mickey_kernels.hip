@@ -29,7 +29,7 @@ using namespace mickey_host;
 namespace {
 
 constexpr int kUnroll = 4;  // clocks per loop iteration of the generate kernels
-constexpr int kSplitWaves = 2;   // waves per SIMD the split kernel is compiled for
+constexpr int kSplitWaves = 4;   // waves per SIMD the split kernel is compiled for (128 VGPRs)
 constexpr int kSplit4Waves = 4;  // ... and the four-wave split (128 VGPRs)
 
 // ------------------------------------------------------------------------ kernels
@@ -212,13 +212,21 @@ gen_split_kernel(uint32_t *__restrict__ state, uint32_t nslices, uint32_t n, uin
         Word<1> r33 = {{xl.r33[0][lane]}};
         __builtin_amdgcn_sched_barrier(0);
         // the same clock count and buffer sequence as the R wave (one barrier per clock);
-        // an even unroll lets the S words alternate between two register sets, no copies
+        // ascending and descending sweeps alternate, so the S words keep one register set
+        static_assert(kUnroll % 2 == 0, "sweeps alternate in pairs");
         uint64_t t = 0;
         for (; t + kUnroll <= nbits; t += kUnroll) {
 #pragma unroll
-            for (int u = 0; u < kUnroll; u++) split_s_clock(x, r33, xl, lane, (u + 1) & 1);
+            for (int u = 0; u < kUnroll; u += 2) {
+                split_s_clock(x, r33, xl, lane, 1);
+                split_s_clock_desc(x, r33, xl, lane, 0);
+            }
         }
-        for (; t < nbits; t++) split_s_clock(x, r33, xl, lane, (int)((t + 1) & 1));
+        // at most kUnroll - 1 = 3 clocks left, starting on an even clock (straight-line, so
+        // the registers need not return to their loop positions)
+        if (t < nbits) split_s_clock(x, r33, xl, lane, 1);
+        if (t + 1 < nbits) split_s_clock_desc(x, r33, xl, lane, 0);
+        if (t + 2 < nbits) split_s_clock(x, r33, xl, lane, 1);
         uint32_t v = voff;
         asm volatile("" : "+v"(v));
 #pragma unroll
