@@ -273,6 +273,55 @@ def bench_aes(torch, mickey, synth, reps: int = 3):
             "hbm_frac": round(bits / 8 / (tg * 1e-3) / 8e12, 4)}
 
 
+def bench_mickey128(torch, mickey, synth, reps: int = 5, ncheck: int = 16):
+    """Bitsliced MICKEY-128 2.0: 3 * 2^20 instances (splitmix64 seed 8, 128-bit keys and
+    IVs), 8192 bits each into bit-planes (3 GiB); the R and S waves of each 64 slices run
+    three waves per SIMD.  VALU-bound at 518 ops per clock for 32 instances.  ncheck
+    seeded instances are compared with the oracle at full length."""
+    from oracle import mickey128 as m128_oracle
+    seed, n, nbits, _ = synth.workload("mickey128-3m")
+    keys, ivs = synth.keys_ivs128(seed, n)
+    dk, dv = torch.from_numpy(keys).cuda(), torch.from_numpy(ivs).cuda()
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    m = mickey.Mickey128(dk, dv, stream=stream)
+    m.sync()
+    init_wall = time.perf_counter() - t0
+    out = torch.empty(nbits * m.pitch, dtype=torch.uint8, device="cuda")
+    m.generate(nbits, out)  # warm-up
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for k in range(reps):
+        m.generate(nbits, out)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    tg = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]))
+    # after the warm-up and reps calls the output holds each stream's clocks
+    # reps * nbits .. (reps + 1) * nbits - 1
+    rng = np.random.default_rng(1280)
+    idx = np.sort(rng.choice(n, ncheck, replace=False))
+    planes = out.view(nbits, m.pitch)
+    ti = torch.from_numpy(idx // 8).cuda()
+    sh = torch.from_numpy(idx % 8).cuda().to(torch.uint8)
+    got = ((planes[:, ti] >> sh) & 1).T.cpu().numpy()
+    m.close()
+    del out
+    rows = m128_oracle.generate_many(keys[idx], ivs[idx], None, nbits, skip=reps * nbits, threads=8)
+    want = np.unpackbits(rows, axis=1)[:, :nbits]
+    mism = int((got != want).any(axis=1).sum())
+    bits = n * nbits
+    ops = mickey.mickey128_ops_per_clock() * (n // 32) * nbits
+    print("# mickey128-3m: generate %.3f ms, oracle check %d/%d" % (tg, ncheck - mism, ncheck), file=sys.stderr,
+          flush=True)
+    return {"workload": "mickey128-3m: 3*2^20 MICKEY-128 2.0 instances (stand-in S tables), 128-bit keys and "
+                        "IVs (splitmix64 seed 8), 8192 bits each, bitsliced planes",
+            "generate_ms": round(tg, 4), "generate_gbit_s": round(bits / (tg * 1e-3) / 1e9, 3),
+            "init_wall_ms": round(init_wall * 1e3, 2),
+            "valu_frac": round(ops / (tg * 1e-3) / 78.6432e12, 4),
+            "ops_per_clock_per_32": mickey.mickey128_ops_per_clock(),
+            "oracle_check": {"instances": ncheck, "bits_each": nbits, "mismatches": mism}}
+
+
 def bench_batch(torch, mickey, synth, oracle_runs=None, tune_cap_bits: int = 4096, nsample: int = 12,
                 n_longest: int = 16, n_other: int = 48):
     """10,000 fresh requests (seed 4): IV lengths 0..80, lengths log-uniform in
@@ -733,6 +782,7 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true", help="skip the served measurements")
     ap.add_argument("--no-grain", action="store_true", help="skip the bitsliced Grain leg")
     ap.add_argument("--no-aes", action="store_true", help="skip the bitsliced AES-CTR leg")
+    ap.add_argument("--no-mickey128", action="store_true", help="skip the bitsliced MICKEY-128 2.0 leg")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="Poisson arrival window of the served run")
     ap.add_argument("--serve-max-kib", type=int, default=64 << 10, help="largest served request (KiB)")
     ap.add_argument("--serve-drain", type=float, default=90.0,
@@ -886,6 +936,8 @@ def main() -> int:
         res["grain_4m"] = bench_grain(torch, mickey, synth)
     if not args.no_aes:
         res["aes_4m"] = bench_aes(torch, mickey, synth)
+    if not args.no_mickey128:
+        res["mickey128_3m"] = bench_mickey128(torch, mickey, synth)
     # the oracle's runs on sampled batched and served requests (part of the cpu_baseline leg)
     # go on host threads while the GPU works; they also check those requests' outputs
     # (half the host threads: the server's host loop and the GPU runtime need the rest)

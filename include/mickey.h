@@ -167,9 +167,10 @@ int mickey_set_word_bits(mickey_state *st, int word_bits);
  *                          S and computing first the values the others need (10 words
  *                          exchanged per clock); 128 VGPRs per wave.  Bit-planes only:
  *                          the fused row-major path runs SPLIT instead.  32-bit words only;
- *   MICKEY_SCHED_AUTO      (default) SPLIT4 when word_bits is 32 and the one-wave launch
- *                          would leave SIMDs with fewer than two waves (n < 2^22 on
- *                          MI355X), else ONE_WAVE. */
+ *   MICKEY_SCHED_AUTO      (default) with 32-bit words: ONE_WAVE when the one-wave launch
+ *                          gives every SIMD two waves (n >= 2^22 on MI355X), SPLIT when it
+ *                          gives every SIMD at least one (n >= 2^21), SPLIT4 below; with
+ *                          64-bit words ONE_WAVE. */
 #define MICKEY_SCHED_AUTO 0
 #define MICKEY_SCHED_ONE_WAVE 1
 #define MICKEY_SCHED_SPLIT 2

@@ -661,11 +661,12 @@ mickey_state *init_impl(const uint8_t *keys, const uint8_t *ivs, const uint8_t *
 }
 
 // Which kernel generates: the split schedules multiply the waves of a call by 2 or 4 at the
-// cost of a per-clock exchange.  Measured on MI355X (1024 SIMDs, bit-planes, 4096 clocks),
-// against the one-wave kernel: four-wave split 2.3x at 2^18 instances, 2.0x at 2^20, 1.2x
-// at 2^21 (the two-wave split is equal there), 1.07x at 3*2^20, 0.94x at 2^22 where the
-// one-wave kernel fills every SIMD with two waves.  The automatic schedule takes the
-// four-wave split below that point.
+// cost of a per-clock exchange.  Measured on MI355X (1024 SIMDs, bit-planes, 8192 clocks;
+// ms): at 2^22 instances one-wave 6.95, two-wave split 7.50, four-wave split 7.76 (the
+// one-wave kernel fills every SIMD with two waves); at 2^21 5.00, 3.84, 4.05 (the two-wave
+// split, at 128 VGPRs, puts two waves on every SIMD); at 2^20 5.08, 3.49, 2.20.  The
+// automatic schedule follows: one-wave from two one-wave waves per SIMD, the two-wave
+// split from one, the four-wave split below.
 enum class Gen { OneWave, Split2, Split4 };
 
 Gen pick_gen(const mickey_state *st)
@@ -674,7 +675,8 @@ Gen pick_gen(const mickey_state *st)
     if (st->schedule == MICKEY_SCHED_SPLIT) return Gen::Split2;
     if (st->schedule == MICKEY_SCHED_SPLIT4) return Gen::Split4;
     const size_t waves = (st->nslices + 63) / 64;
-    return waves < 2 * (size_t)st->simds ? Gen::Split4 : Gen::OneWave;
+    if (waves >= 2 * (size_t)st->simds) return Gen::OneWave;
+    return waves >= (size_t)st->simds ? Gen::Split2 : Gen::Split4;
 }
 
 bool use_split4(const mickey_state *st) { return pick_gen(st) == Gen::Split4; }
