@@ -1,10 +1,10 @@
 """CPU builds of the host-side C and C++ under AddressSanitizer and UndefinedBehaviorSanitizer.
 
-- The three oracles (oracle/*.c) are compiled into small drivers that run their
-  known-answer vectors (tests/golden), every IV length 0..80, multi-instance generation
-  with skips and the state pack/unpack round trip; the drivers print the keystreams,
-  which must equal the published vectors.  Any out-of-bounds access or undefined
-  operation aborts the driver.
+- The oracles (oracle/*.c) are compiled into small drivers that run their known-answer
+  vectors (tests/golden), every IV length, multi-instance generation with skips and the
+  state packing; the drivers print the keystreams, which must equal the published
+  vectors (for MICKEY-128 2.0, which has none here, the ordinary build's output).  Any
+  out-of-bounds access or undefined operation aborts the driver.
 - The serving allocator (csrc/arena.h) runs the random alloc/release sequences of
   tests/test_arena.py.
 Host code only: nothing here touches a GPU.
@@ -108,6 +108,30 @@ int main(int argc, char **argv)
 """
 
 
+MICKEY128_DRIVER = r"""
+#include "mickey128_ref.c"
+#include <stdio.h>
+static void hex(const uint8_t *p, size_t n) { for (size_t i = 0; i < n; i++) printf("%02x", p[i]); printf("\n"); }
+int main(void)
+{
+    /* every IV length 0..128 with a skip, the packed state, a rejected length */
+    static uint8_t keys[129 * 16], ivs[129 * 16], lens[129], rows[129 * 13];
+    for (int i = 0; i < 129 * 16; i++) { keys[i] = (uint8_t)(i * 37 + 11); ivs[i] = (uint8_t)(i * 91 + 5); }
+    for (int i = 0; i < 129; i++) lens[i] = (uint8_t)i;
+    if (m128_generate_many(keys, ivs, lens, 129, 17, 100, rows) != 0) return 3;
+    for (int i = 0; i < 129; i += 32) hex(rows + 13 * i, 13);
+    m128_state st;
+    uint8_t packed[40];
+    m128_init(&st, keys, ivs, 128);
+    m128_pack_state(&st, packed);
+    hex(packed, 40);
+    lens[3] = 129;
+    if (m128_generate_many(keys, ivs, lens, 129, 0, 8, rows) != -1) return 4;
+    return 0;
+}
+"""
+
+
 def golden(name):
     rows = []
     for line in open(os.path.join(GOLDEN, name)):
@@ -156,6 +180,20 @@ def test_aes_oracle_under_sanitizers(tmp_path):
         args += [b["key"], b["in"]]
     out = build_and_run(tmp_path, "aes_san", AES_DRIVER, "c", args)
     assert out == [b["out"] for b in blocks]
+
+
+def test_mickey128_oracle_under_sanitizers(tmp_path):
+    import numpy as np
+
+    from oracle import mickey128 as m128
+    out = build_and_run(tmp_path, "mickey128_san", MICKEY128_DRIVER, "c", [])
+    i = np.arange(129 * 16)
+    keys = ((i * 37 + 11) % 256).astype(np.uint8).reshape(129, 16)
+    ivs = ((i * 91 + 5) % 256).astype(np.uint8).reshape(129, 16)
+    rows = m128.generate_many(keys, ivs, np.arange(129, dtype=np.uint8), 100, skip=17)
+    st = m128.State()
+    st.init(keys[0].tobytes(), ivs[0].tobytes(), 128)
+    assert out == [rows[k].tobytes().hex() for k in range(0, 129, 32)] + [st.packed().hex()]
 
 
 def test_arena_under_sanitizers(tmp_path):
