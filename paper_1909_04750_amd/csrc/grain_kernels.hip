@@ -106,8 +106,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 }
 
 // Keystream into bit-planes: plane t (pitch = nslices words) gets z_t of every instance.
-// RINGS rings of 80 clocks form one loop iteration (two let the register allocator close
-// the loop without copies).
+#define GRAIN_LOOP_B(j) x.b[j]
+#define GRAIN_LOOP_S(j) x.s[j]
+#include "grain_clock_loop.inc"
+
+// Keystream into bit-planes (RINGS is kept for the launch; the generated loop runs one ring
+// revolution per iteration).
 template <int RINGS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void grain_gen_kernel(
     uint32_t *__restrict__ planes, uint32_t nslices, uint64_t nbits, uint32_t *__restrict__ out)
@@ -123,12 +127,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         store_plane_word(plane, voff, z);
         plane += pitch;
     };
-    for (uint64_t it = nbits / (RINGS * kRing); it != 0; --it) {
-#pragma unroll
-        for (int r = 0; r < RINGS; r++) clocks80<false>(x, emit);
+    // One ring revolution (80 clocks) per iteration of the loop generated by
+    // gen_grain_loop.py, with the ring slots in VGPRs chosen for the register banks; the
+    // plane stores go through a buffer resource in s[20:23] whose base advances by the
+    // pitch every clock, and s24 counts iterations.  The window is back in canonical order
+    // after each revolution.
+    for (uint64_t left = nbits / kRing; left != 0;) {
+        const uint32_t iters = left > (1u << 30) ? (1u << 30) : (uint32_t)left;
+        const uint64_t base = (uint64_t)(uintptr_t)plane;
+        asm volatile("s_mov_b32 s20, %[lo]\n\t"
+                     "s_and_b32 s21, %[hi], 0xffff\n\t"
+                     "s_mov_b32 s22, 0x7fffffff\n\t"
+                     "s_mov_b32 s23, 0x20000\n\t"
+                     "s_mov_b32 s24, %[it]\n"
+                     "1:\n\t" GRAIN_LOOP_BODY
+                     "\ts_sub_u32 s24, s24, 1\n\t"
+                     "s_cmp_lg_u32 s24, 0\n\t"
+                     "s_cbranch_scc1 1b"
+                     : GRAIN_LOOP_STATE(GRAIN_LOOP_B, GRAIN_LOOP_S)
+                     : [lo] "s"((uint32_t)base), [hi] "s"((uint32_t)(base >> 32)), [pitch] "s"((uint32_t)pitch),
+                       [it] "s"(iters), [voff] "v"(voff)
+                     : GRAIN_LOOP_CLOBBERS, "s20", "s21", "s22", "s23", "s24", "scc");
+        left -= iters;
+        plane += (uint64_t)iters * kRing * pitch;
     }
-#pragma unroll 1
-    for (uint64_t t = (nbits / kRing) % RINGS; t != 0; --t) clocks80<false>(x, emit);
 #pragma unroll 1
     for (uint64_t t = nbits % kRing; t != 0; --t) emit(0, clock_shift(x));
     store_planes(x, planes, nslices, g);

@@ -1,0 +1,67 @@
+"""Register-level emulator of the few gfx950 instructions the generated clock loops use
+(v_bitop3_b32, v_xor_b32, v_and_b32, v_mov_b32, buffer_store_dword and the scalar address
+updates), for CPU tests of the loops in paper_1909_04750_amd/csrc/*_clock_loop.inc."""
+import re
+
+import numpy as np
+
+
+def parse_inc(path, prefix):
+    """(clocks, instructions, homes) of a generated loop file; homes are (vgpr, kind, index)
+    from its state operand list."""
+    text = open(path).read()
+    clocks = int(re.search(r"#define %s_LOOP_CLOCKS (\d+)" % prefix, text).group(1))
+    body = re.search(r"#define %s_LOOP_BODY \\\n(.*?)\n#define" % prefix, text, re.S).group(1)
+    insts = [s.replace("\\t", "").replace("\\n", "").strip() for s in re.findall(r'"(.*?)"', body)]
+    insts = [i for i in insts if i]
+    homes = [(int(v), kind, int(idx)) for v, kind, idx in re.findall(r'"\+\{v(\d+)\}"\(([A-Z])\((\d+)\)\)', text)]
+    return clocks, insts, homes
+
+
+def emulate(insts, regs):
+    """Run the instructions once on `regs` (dict vN -> uint32 array); returns the stored
+    words in order."""
+    stored = []
+    for ins in insts:
+        op, _, rest = ins.partition(" ")
+        if op in ("s_add_u32", "s_addc_u32"):
+            continue
+        args = [a.strip() for a in rest.split(",")]
+        if op == "buffer_store_dword":
+            stored.append(regs[int(args[0][1:])].copy())
+            continue
+        if op == "v_bitop3_b32":
+            d, a, b, c = (int(x.split()[0][1:]) for x in args[:4])
+            imm = int(args[3].split("bitop3:")[1], 16)
+            va, vb, vc = regs[a], regs[b], regs[c]
+            out = np.zeros_like(va)
+            for m in range(8):
+                if imm >> m & 1:
+                    out |= (va if m & 4 else ~va) & (vb if m & 2 else ~vb) & (vc if m & 1 else ~vc)
+            regs[d] = out
+        elif op in ("v_xor_b32", "v_and_b32"):
+            d, a, b = (int(x[1:]) for x in args)
+            regs[d] = regs[a] ^ regs[b] if op == "v_xor_b32" else regs[a] & regs[b]
+        elif op == "v_mov_b32":
+            d, a = (int(x[1:]) for x in args)
+            regs[d] = regs[a].copy()
+        else:
+            raise AssertionError("unexpected instruction " + ins)
+    return stored
+
+
+def written_before_read(insts, homes):
+    """True if every register an instruction reads is a home register or was written by an
+    earlier instruction of the body."""
+    written = {v for v, _, _ in homes}
+    for ins in insts:
+        op, _, rest = ins.partition(" ")
+        if not op.startswith("v_"):
+            if op == "buffer_store_dword" and int(rest.split(",")[0].strip()[1:]) not in written:
+                return False
+            continue
+        regs = [int(x.strip().split()[0][1:]) for x in rest.split(",")]
+        if any(src not in written for src in regs[1:]):
+            return False
+        written.add(regs[0])
+    return True

@@ -10,11 +10,11 @@
 """
 import importlib.util
 import os
-import re
 
 import numpy as np
 
 import oracle
+from tests import asm_emulator
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1909_04750_amd", "csrc")
@@ -29,45 +29,10 @@ def generator():
 
 
 def parse_inc():
-    text = open(INC).read()
-    clocks = int(re.search(r"#define MICKEY_LOOP_CLOCKS (\d+)", text).group(1))
-    body = re.search(r"#define MICKEY_LOOP_BODY \\\n(.*?)\n#define", text, re.S).group(1)
-    insts = [s.replace("\\t", "").replace("\\n", "").strip() for s in re.findall(r'"(.*?)"', body)]
-    insts = [i for i in insts if i]
-    homes = [(int(v), kind, int(idx)) for v, kind, idx in
-             re.findall(r'"\+\{v(\d+)\}"\(([RS])\((\d+)\)\)', text)]
-    return clocks, insts, homes
+    return asm_emulator.parse_inc(INC, "MICKEY")
 
 
-def emulate(insts, regs):
-    """Run one loop iteration on `regs` (dict vN -> uint32 array); returns stored words."""
-    stored = []
-    for ins in insts:
-        op, _, rest = ins.partition(" ")
-        if op in ("s_add_u32", "s_addc_u32"):
-            continue
-        args = [a.strip() for a in rest.split(",")]
-        if op == "buffer_store_dword":
-            stored.append(regs[int(args[0][1:])].copy())
-            continue
-        if op == "v_bitop3_b32":
-            d, a, b, c = (int(x.split()[0][1:]) for x in args[:4])
-            imm = int(args[3].split("bitop3:")[1], 16)
-            va, vb, vc = regs[a], regs[b], regs[c]
-            out = np.zeros_like(va)
-            for m in range(8):
-                if imm >> m & 1:
-                    out |= (va if m & 4 else ~va) & (vb if m & 2 else ~vb) & (vc if m & 1 else ~vc)
-            regs[d] = out
-        elif op in ("v_xor_b32", "v_and_b32"):
-            d, a, b = (int(x[1:]) for x in args)
-            regs[d] = regs[a] ^ regs[b] if op == "v_xor_b32" else regs[a] & regs[b]
-        elif op == "v_mov_b32":
-            d, a = (int(x[1:]) for x in args)
-            regs[d] = regs[a].copy()
-        else:
-            raise AssertionError("unexpected instruction " + ins)
-    return stored
+emulate = asm_emulator.emulate
 
 
 def test_committed_loop_matches_generator():
@@ -76,17 +41,7 @@ def test_committed_loop_matches_generator():
 
 def test_temporaries_written_before_read():
     _, insts, homes = parse_inc()
-    written = {v for v, _, _ in homes}
-    for ins in insts:
-        op, _, rest = ins.partition(" ")
-        if not op.startswith("v_"):
-            if op == "buffer_store_dword":
-                assert int(rest.split(",")[0].strip()[1:]) in written
-            continue
-        regs = [int(x.strip().split()[0][1:]) for x in rest.split(",")]
-        for src in regs[1:]:
-            assert src in written, ins
-        written.add(regs[0])
+    assert asm_emulator.written_before_read(insts, homes)
 
 
 def test_loop_body_equals_oracle_clocks():
