@@ -102,6 +102,18 @@ class OracleRuns:
         self.pool.shutdown(wait=True)
 
 
+def warm_up(torch, fn, seconds: float = 0.5):
+    """Run fn until `seconds` of wall time have passed (at least twice), so that a leg is
+    timed at the engine clock the device settles at under that kernel, not at the clock
+    it idled at before."""
+    t0 = time.perf_counter()
+    k = 0
+    while k < 2 or time.perf_counter() - t0 < seconds:
+        fn()
+        torch.cuda.synchronize()
+        k += 1
+
+
 def words_be_bytes(words: np.ndarray) -> bytes:
     """Row-major words as the oracle's MSB-first byte stream (bit 31-b of word j is bit
     32j+b, so a word's big-endian bytes are 4 consecutive stream bytes)."""
@@ -213,7 +225,7 @@ def bench_grain(torch, mickey, synth, reps: int = 5):
     stream = torch.cuda.current_stream()
     g = mickey.Grain(dk, dv, stream=stream)
     out = torch.empty(nbits * g.pitch, dtype=torch.uint8, device="cuda")
-    g.generate(nbits, mickey.BITSLICED, out)  # warm-up
+    warm_up(torch, lambda: g.generate(nbits, mickey.BITSLICED, out))
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     t_init, t_gen = [], []
     for _ in range(reps):
@@ -250,7 +262,7 @@ def bench_aes(torch, mickey, synth, reps: int = 3):
     stream = torch.cuda.current_stream()
     a = mickey.AesCtr(dk, dn, stream=stream)
     out = torch.empty(nbits * a.pitch, dtype=torch.uint8, device="cuda")
-    a.generate(nbits, mickey.BITSLICED, out)  # warm-up
+    warm_up(torch, lambda: a.generate(nbits, mickey.BITSLICED, out))
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     t_gen = []
     for _ in range(reps):
@@ -288,7 +300,7 @@ def bench_mickey128(torch, mickey, synth, reps: int = 5, ncheck: int = 16):
     m.sync()
     init_wall = time.perf_counter() - t0
     out = torch.empty(nbits * m.pitch, dtype=torch.uint8, device="cuda")
-    m.generate(nbits, out)  # warm-up
+    warm_up(torch, lambda: m.generate(nbits, out))
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
     ev[0].record(stream)
     for k in range(reps):
@@ -296,8 +308,8 @@ def bench_mickey128(torch, mickey, synth, reps: int = 5, ncheck: int = 16):
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     tg = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]))
-    # after the warm-up and reps calls the output holds each stream's clocks
-    # reps * nbits .. (reps + 1) * nbits - 1
+    # the output holds each stream's last nbits clocks
+    skip = m.bits_generated - nbits
     rng = np.random.default_rng(1280)
     idx = np.sort(rng.choice(n, ncheck, replace=False))
     planes = out.view(nbits, m.pitch)
@@ -306,7 +318,7 @@ def bench_mickey128(torch, mickey, synth, reps: int = 5, ncheck: int = 16):
     got = ((planes[:, ti] >> sh) & 1).T.cpu().numpy()
     m.close()
     del out
-    rows = m128_oracle.generate_many(keys[idx], ivs[idx], None, nbits, skip=reps * nbits, threads=8)
+    rows = m128_oracle.generate_many(keys[idx], ivs[idx], None, nbits, skip=skip, threads=8)
     want = np.unpackbits(rows, axis=1)[:, :nbits]
     mism = int((got != want).any(axis=1).sum())
     bits = n * nbits

@@ -19,16 +19,40 @@ def parse_inc(path, prefix):
 
 
 def emulate(insts, regs):
-    """Run the instructions once on `regs` (dict vN -> uint32 array); returns the stored
-    words in order."""
+    """Run the instructions once on `regs` (dict vN -> uint32 array over lanes); returns the
+    keystream words in clock order, each an array over lanes.
+
+    LDS and the 16-byte stores follow the generated loops' quad regrouping: lane l writes
+    its clock word at byte l*4 + 256*(clock % 4) (%[zaddr] = 4*l), reads 16 bytes at
+    ((l % 4)*64 + l - l % 4)*4 (%[qaddr]), and a buffer_store_dwordx4 by lane l holds clock
+    (4*group + l % 4)'s words of the lanes of its quad.  The lane count must be a multiple
+    of 4 when the loop uses these instructions."""
+    lanes = len(next(iter(regs.values())))
+    lds = np.zeros(4 * 64, dtype=np.uint32)
     stored = []
     for ins in insts:
         op, _, rest = ins.partition(" ")
-        if op in ("s_add_u32", "s_addc_u32"):
+        if op in ("s_add_u32", "s_addc_u32", "s_waitcnt"):
             continue
         args = [a.strip() for a in rest.split(",")]
         if op == "buffer_store_dword":
             stored.append(regs[int(args[0][1:])].copy())
+            continue
+        if op == "ds_write_b32":
+            v = regs[int(args[1].split()[0][1:])]
+            off = int(args[1].split("offset:")[1]) if "offset:" in args[1] else 0
+            for l in range(lanes):
+                lds[(4 * l + off) // 4] = v[l]
+            continue
+        if op == "ds_read_b128":
+            lo, hi = (int(x) for x in re.match(r"v\[(\d+):(\d+)\]", args[0]).groups())
+            for k in range(4):
+                regs[lo + k] = np.array([lds[(l % 4) * 64 + l - l % 4 + k] for l in range(lanes)], dtype=np.uint32)
+            continue
+        if op == "buffer_store_dwordx4":
+            lo = int(re.match(r"v\[(\d+):", args[0]).group(1))
+            for q in range(4):  # clock q of the group: lane 4j+q holds slice 4j+k's word in register lo+k
+                stored.append(np.array([regs[lo + l % 4][l - l % 4 + q] for l in range(lanes)], dtype=np.uint32))
             continue
         if op == "v_bitop3_b32":
             d, a, b, c = (int(x.split()[0][1:]) for x in args[:4])
@@ -56,9 +80,21 @@ def written_before_read(insts, homes):
     written = {v for v, _, _ in homes}
     for ins in insts:
         op, _, rest = ins.partition(" ")
-        if not op.startswith("v_"):
-            if op == "buffer_store_dword" and int(rest.split(",")[0].strip()[1:]) not in written:
+        if op in ("buffer_store_dword", "ds_write_b32"):
+            data = rest.split(",")[0 if op == "buffer_store_dword" else 1].strip().split()[0]
+            if int(data[1:]) not in written:
                 return False
+            continue
+        if op == "ds_read_b128":
+            lo, hi = (int(x) for x in re.match(r"v\[(\d+):(\d+)\]", rest).groups())
+            written.update(range(lo, hi + 1))
+            continue
+        if op == "buffer_store_dwordx4":
+            lo, hi = (int(x) for x in re.match(r"v\[(\d+):(\d+)\]", rest).groups())
+            if any(r not in written for r in range(lo, hi + 1)):
+                return False
+            continue
+        if not op.startswith("v_"):
             continue
         regs = [int(x.strip().split()[0][1:]) for x in rest.split(",")]
         if any(src not in written for src in regs[1:]):

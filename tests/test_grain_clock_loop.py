@@ -40,7 +40,7 @@ def test_loop_body_equals_oracle_clocks():
     clocks, insts, homes = asm_emulator.parse_inc(INC, "GRAIN")
     assert len(homes) == 160
     rng = np.random.default_rng(80)
-    lanes, iters = 2, 2
+    lanes, iters = 4, 2
     regs = {v: rng.integers(0, 2 ** 32, lanes, dtype=np.uint64).astype(np.uint32) for v in range(256)}
     start = {(k, i): regs[v].copy() for v, k, i in homes}
     stored = []
@@ -48,7 +48,7 @@ def test_loop_body_equals_oracle_clocks():
         stored += asm_emulator.emulate(insts, regs)
     assert len(stored) == clocks * iters
     for lane in range(lanes):
-        for bit in (0, 9, 22, 31):
+        for bit in (0, 22, 31):
             st = grain_oracle.State()
             st.b[:] = [(int(start[("B", i)][lane]) >> bit) & 1 for i in range(80)]
             st.s[:] = [(int(start[("S", i)][lane]) >> bit) & 1 for i in range(80)]
