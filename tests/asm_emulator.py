@@ -18,7 +18,7 @@ def parse_inc(path, prefix):
     return clocks, insts, homes
 
 
-def emulate(insts, regs):
+def emulate(insts, regs, lds=None, addr=None):
     """Run the instructions once on `regs` (dict vN -> uint32 array over lanes); returns the
     keystream words in clock order, each an array over lanes.
 
@@ -28,11 +28,20 @@ def emulate(insts, regs):
     (4*group + l % 4)'s words of the lanes of its quad.  The lane count must be a multiple
     of 4 when the loop uses these instructions."""
     lanes = len(next(iter(regs.values())))
-    lds = np.zeros(4 * 64, dtype=np.uint32)
+    if lds is None:
+        lds = np.zeros(4 * 64, dtype=np.uint32)
+    if addr is None:  # the quad regrouping's LDS addresses
+        addr = {"zaddr": np.arange(lanes) * 4,
+                "qaddr": np.array([((l % 4) * 64 + l - l % 4) * 4 for l in range(lanes)])}
     stored = []
+
+    def lds_index(arg, lane):
+        name = re.search(r"%\[(\w+)\]", arg).group(1)
+        off = int(arg.split("offset:")[1]) if "offset:" in arg else 0
+        return (int(addr[name][lane]) + off) // 4
     for ins in insts:
         op, _, rest = ins.partition(" ")
-        if op in ("s_add_u32", "s_addc_u32", "s_waitcnt"):
+        if op in ("s_add_u32", "s_addc_u32", "s_waitcnt", "s_barrier"):
             continue
         args = [a.strip() for a in rest.split(",")]
         if op == "buffer_store_dword":
@@ -40,14 +49,17 @@ def emulate(insts, regs):
             continue
         if op == "ds_write_b32":
             v = regs[int(args[1].split()[0][1:])]
-            off = int(args[1].split("offset:")[1]) if "offset:" in args[1] else 0
             for l in range(lanes):
-                lds[(4 * l + off) // 4] = v[l]
+                lds[lds_index(rest, l)] = v[l]
+            continue
+        if op == "ds_read_b32":
+            d = int(args[0][1:])
+            regs[d] = np.array([lds[lds_index(rest, l)] for l in range(lanes)], dtype=np.uint32)
             continue
         if op == "ds_read_b128":
             lo, hi = (int(x) for x in re.match(r"v\[(\d+):(\d+)\]", args[0]).groups())
             for k in range(4):
-                regs[lo + k] = np.array([lds[(l % 4) * 64 + l - l % 4 + k] for l in range(lanes)], dtype=np.uint32)
+                regs[lo + k] = np.array([lds[lds_index(rest, l) + k] for l in range(lanes)], dtype=np.uint32)
             continue
         if op == "buffer_store_dwordx4":
             lo = int(re.match(r"v\[(\d+):", args[0]).group(1))
@@ -88,6 +100,9 @@ def written_before_read(insts, homes):
         if op == "ds_read_b128":
             lo, hi = (int(x) for x in re.match(r"v\[(\d+):(\d+)\]", rest).groups())
             written.update(range(lo, hi + 1))
+            continue
+        if op == "ds_read_b32":
+            written.add(int(rest.split(",")[0].strip()[1:]))
             continue
         if op == "buffer_store_dwordx4":
             lo, hi = (int(x) for x in re.match(r"v\[(\d+):(\d+)\]", rest).groups())
