@@ -28,6 +28,7 @@
 #include "mickey_device.h"
 #include "mickey_host.h"
 #include "mickey_pack.h"
+#include "mickey_split4_loop.h"
 #include "mickey_wordpar.h"
 
 #include <hip/hip_runtime.h>
@@ -675,28 +676,12 @@ __device__ __forceinline__ void serve4_run(uint32_t *__restrict__ planes, size_t
     if constexpr (ROLE == 0) {
         if (fr0) fresh[g] = 0u;  // every wave read it before the barrier
     }
-    auto clock = [&](auto ph) {
-        constexpr int PH = decltype(ph)::value;
-        if constexpr (ROLE == 0) s4_clock_rlo<PH>(x, in, xl, lane);
-        else if constexpr (ROLE == 1) s4_clock_rhi<PH>(x, in, xl, lane);
-        else if constexpr (ROLE == 2) s4_clock_slo<PH>(x, in, xl, lane);
-        else s4_clock_shi<PH>(x, in, xl, lane);
-    };
     char *plane = (char *)zplanes;  // wave-uniform (wave 0)
     uint32_t blk = 0;
     for (; blk < nblocks && active; blk++) {
-        for (int c = 0; c < 32; c += 2) {  // clock t writes exchange buffer (t + 1) & 1
-            if constexpr (ROLE == 0) {
-                store_plane<1>(plane, voff, x.r[0] ^ in.d);
-                plane += pitch;
-            }
-            clock(std::integral_constant<int, 1>{});
-            if constexpr (ROLE == 0) {
-                store_plane<1>(plane, voff, x.r[0] ^ in.d);
-                plane += pitch;
-            }
-            clock(std::integral_constant<int, 0>{});
-        }
+        // the block's 32 clocks as 16 pairs (clock t writes exchange buffer (t + 1) & 1)
+        s4_pairs<ROLE>(x, in, xl, lane, plane, voff, (uint32_t)pitch, 16u);
+        plane += 32 * pitch;
         if (blk + 1u == next_end) {
             const uint32_t finished = ending_lanes(lane_left, g, active, blk, next_end);
             for (uint32_t l = 0; l < 32; l++) {
