@@ -96,8 +96,13 @@ def role_body(role, tab):
     for name, _ in imports:
         for p in (0, 1):
             imp[p][name] = take(import_avoid(name))
-    cra, crb = take(avoid=(1, 2, 3)), take(avoid=(0, 1, 3))
-    cs, g0, g1, zreg = take(), take(), take(), take()
+    # per clock parity, so that the next clock's control bits do not wait for the current
+    # clock's last reader
+    ctl = [(take(avoid=(1, 2, 3)), take(avoid=(0, 1, 3)), take(), take(), take()) for _ in (0, 1)]
+    # the wave that owns position 99 reads the feedback bit from a copy: the next clock's
+    # export of that position then need not wait for the current clock's last tap
+    fb_copy = [take(), take()] if 99 in own else None
+    zreg = take()
     regions = [[], [], []]  # before barrier 1 | between barriers | after barrier 2
 
     def emit(region, kind, text, dsts, srcs):
@@ -112,6 +117,7 @@ def role_body(role, tab):
     for t in (0, 1):
         cur, nxt = sets[t], sets[1 - t]
         im, im_next = imp[t], imp[1 - t]
+        cra, crb, cs, g0, g1 = ctl[t]
         ph = 1 - t                     # clock t writes exchange buffer (t + 1) & 1
         pre, post = t, t + 1           # region before this clock's barrier, region after it
 
@@ -122,6 +128,9 @@ def role_body(role, tab):
 
         if reg == "r":
             fbr = src_of("r99")
+            if fb_copy:
+                emit(pre, "valu", "v_mov_b32 v%d, v%d" % (fb_copy[t], fbr), [fb_copy[t]], [fbr])
+                fbr = fb_copy[t]
             v2(pre, "v_xor_b32", cra, src_of("s34"), src_of("r67"))
             v2(pre, "v_xor_b32", crb, src_of("s34"), src_of("r67"))
             if role == 0:  # keystream word of the current state
@@ -144,6 +153,9 @@ def role_body(role, tab):
                     r_update(i, post)
         else:
             fbs = src_of("s99")
+            if fb_copy:
+                emit(pre, "valu", "v_mov_b32 v%d, v%d" % (fb_copy[t], fbs), [fb_copy[t]], [fbs])
+                fbs = fb_copy[t]
             v2(pre, "v_xor_b32", cs, src_of("s67"), src_of("r33"))
             v2(pre, "v_and_b32", g1, fbs, cs)
             v2(pre, "v_xor_b32", g0, fbs, g1)
@@ -222,13 +234,10 @@ def schedule(ops):
     for k in range(n):
         for p, d in preds[k]:
             succs[p].append((k, d))
+    # LDS writes, and everything that computes their data, go first: they gate the barrier
     height = [0] * n
     for k in range(n - 1, -1, -1):
-        height[k] = max([height[s] + d for s, d in succs[k]] or [0])
-    # LDS writes go as early as their data allows (they gate the barrier)
-    for k, o in enumerate(ops):
-        if o.kind == "ldsw":
-            height[k] += 1000
+        height[k] = max([height[s] + d for s, d in succs[k]] + [1000 if ops[k].kind == "ldsw" else 0])
     npred = [len(p) for p in preds]
     ready_at = [0] * n
     avail = [k for k in range(n) if npred[k] == 0]
