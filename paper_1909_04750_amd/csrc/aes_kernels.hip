@@ -191,6 +191,9 @@ __device__ __forceinline__ void mix_add(uint32_t (&st)[16][8], const uint8_t *rk
 // round's working set, they were spilled to scratch and reloaded every block.
 using PreLds = uint32_t[64][64];
 
+#define AES_ST(k, b) st[k][b]
+#include "aes_rounds.inc"
+
 // One block for the slice: counter block N_i || J under round keys rk (176 bytes);
 // pre[8k + b][lane] (k < 8) are the first-round S-box outputs of the nonce bytes.
 __device__ __forceinline__ void encrypt_block(uint32_t (&st)[16][8], const PreLds &pre, uint32_t lane, uint64_t J,
@@ -211,10 +214,14 @@ __device__ __forceinline__ void encrypt_block(uint32_t (&st)[16][8], const PreLd
         }
     }
     mix_add(st, rk + 16);
+    // rounds 2..9: the generated four-round body of aes_rounds.inc (the rounds of
+    // sub_shift<false> + mix_add with registers placed for the VGPR banks), twice; it
+    // loads its four round keys itself from the address it is given
+    static_assert(AES_ROUNDS_COUNT == 4, "rounds 2..9 are two bodies");
 #pragma unroll 1
-    for (int round = 2; round <= 9; round++) {
-        sub_shift<false>(st, nullptr);
-        mix_add(st, rk + 16 * round);
+    for (int q = 0; q < 2; q++) {
+        const uint8_t *rkq = rk + 16 * (2 + AES_ROUNDS_COUNT * q);
+        asm volatile(AES_ROUNDS_BODY : AES_ROUNDS_STATE(AES_ST) : [rk] "s"(rkq) : AES_ROUNDS_CLOBBERS, "memory");
     }
     sub_shift<true>(st, rk + 160);
 }
