@@ -163,4 +163,12 @@ __device__ __forceinline__ void clocks80(State &x, Emit &&emit)
     ring80<INIT>(x, emit, std::make_integer_sequence<int, kRing>{});
 }
 
+// The first n (< 80, wave-uniform) clocks of a revolution from canonical order: afterwards
+// b_j and s_j sit in slot (j + n) % 80.
+template <class Emit, int... R>
+__device__ __forceinline__ void ring_prefix(State &x, uint32_t n, Emit &&emit, std::integer_sequence<int, R...>)
+{
+    ((R < (int)n ? (void)emit(R, clock_ring<R, false>(x)) : (void)0), ...);
+}
+
 }  // namespace grain

@@ -43,12 +43,16 @@ __device__ __forceinline__ void load_planes(State &x, const uint32_t *planes, si
 
 // (Indexed by words: written like this the compiler keeps the clock loops free of
 // spills, which it does not when the offset is laundered through an asm statement.)
-__device__ __forceinline__ void store_planes(const State &x, uint32_t *planes, size_t pitch_words, uint32_t g)
+// rot (wave-uniform, < 80): the window is rot clocks into a revolution, b_j and s_j in
+// slot (j + rot) % 80; the planes are written in canonical order.
+__device__ __forceinline__ void store_planes(const State &x, uint32_t *planes, size_t pitch_words, uint32_t g,
+                                             uint32_t rot = 0)
 {
 #pragma unroll
-    for (int j = 0; j < kRing; j++) {
-        planes[(size_t)j * pitch_words + g] = x.b[j];
-        planes[(size_t)(kRing + j) * pitch_words + g] = x.s[j];
+    for (int k = 0; k < kRing; k++) {
+        const uint32_t j = (uint32_t)k >= rot ? (uint32_t)k - rot : (uint32_t)k + kRing - rot;
+        planes[(size_t)j * pitch_words + g] = x.b[k];
+        planes[(size_t)(kRing + j) * pitch_words + g] = x.s[k];
     }
 }
 
@@ -151,9 +155,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         left -= iters;
         plane += (uint64_t)iters * kRing * pitch;
     }
-#pragma unroll 1
-    for (uint64_t t = nbits % kRing; t != 0; --t) emit(0, clock_shift(x));
-    store_planes(x, planes, nslices, g);
+    // the last nbits % 80 clocks: a revolution's first clocks, then the planes stored
+    // back in canonical order from the rotated window
+    const uint32_t rem = (uint32_t)(nbits % kRing);
+    ring_prefix(x, rem, emit, std::make_integer_sequence<int, kRing>{});
+    store_planes(x, planes, nslices, g, rem);
 }
 
 // 32 clocks of row-major words: zz[b] holds z of clock b for the slice (bit l = lane l);
