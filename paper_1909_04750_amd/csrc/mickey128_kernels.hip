@@ -327,6 +327,10 @@ __device__ __forceinline__ void s_gen_clock(SRegs &x, uint32_t &r53, XLds &xl, u
     __builtin_amdgcn_sched_barrier(0);
 }
 
+#define M128_LOOP_R(i) x.r[i]
+#define M128_LOOP_S(i) x.s[i]
+#include "mickey128_loops.inc"
+
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3, 3))) void m128_gen_kernel(uint32_t *__restrict__ state, uint32_t nslices,
                                                        uint64_t nbits, uint32_t *__restrict__ out)
 {
@@ -335,6 +339,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t g = blockIdx.x * 64u + lane;
     const size_t pitch = (size_t)nslices;
+    const uint32_t xaddr = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint32_t *)&xl.r53[0][lane];
     if (wave == 0) {
         RRegs x;
 #pragma unroll
@@ -346,23 +351,31 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         const size_t pbytes = pitch * 4u;
         const uint32_t voff = g * 4u;
         char *plane = (char *)out;  // wave-uniform
-        uint64_t t = 0;
-        for (; t + 2 <= nbits; t += 2) {
-            mickey::store_plane<1>(plane, voff, {{x.r[0] ^ s0}});
-            plane += pbytes;
-            r_gen_clock<1>(x, s54, s0, xl, lane);
-            mickey::store_plane<1>(plane, voff, {{x.r[0] ^ s0}});
-            plane += pbytes;
-            r_gen_clock<0>(x, s54, s0, xl, lane);
+        // clock pairs: the generated R loop of mickey128_loops.inc (the clocks of
+        // r_gen_clock<1>, r_gen_clock<0> with their plane stores; the buffer resource of the
+        // stores is built in s[20:23])
+        uint64_t npairs = nbits / 2;
+        while (npairs) {
+            const uint32_t iters = npairs > (1ull << 30) ? (1u << 30) : (uint32_t)npairs;
+            const uint64_t base = (uint64_t)(uintptr_t)plane;
+            asm volatile("s_mov_b32 s20, %[lo]\n\ts_and_b32 s21, %[hi], 0xffff\n\ts_mov_b32 s22, 0x7fffffff\n\t"
+                         "s_mov_b32 s23, 0x20000\n\ts_mov_b32 s24, %[it]\n1:\n\t" M128_R_LOOP_BODY
+                         "\n\ts_sub_u32 s24, s24, 1\n\ts_cmp_lg_u32 s24, 0\n\ts_cbranch_scc1 1b"
+                         : M128_R_LOOP_STATE(M128_LOOP_R, s54, s0)
+                         : [lo] "s"((uint32_t)base), [hi] "s"((uint32_t)(base >> 32)), [pitch] "s"((uint32_t)pbytes),
+                           [it] "s"(iters), [voff] "v"(voff), [xaddr] "v"(xaddr)
+                         : M128_R_LOOP_CLOBBERS, "s20", "s21", "s22", "s23", "s24", "scc", "memory");
+            npairs -= iters;
+            plane += (uint64_t)iters * 2 * pbytes;
         }
-        if (t < nbits) {
+        if (nbits & 1) {
             mickey::store_plane<1>(plane, voff, {{x.r[0] ^ s0}});
             r_gen_clock<1>(x, s54, s0, xl, lane);
         }
-        uint32_t v = g;
+        uint32_t v = voff;
         asm volatile("" : "+v"(v));  // keep the load addresses from living across the loop
 #pragma unroll
-        for (int j = 0; j < kN; j++) state[(size_t)j * pitch + v] = x.r[j];
+        for (int j = 0; j < kN; j++) *(uint32_t *)((char *)state + (size_t)j * pbytes + v) = x.r[j];
     } else {
         SRegs x;
 #pragma unroll
@@ -372,16 +385,23 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         mickey::lds_barrier();
         uint32_t r53 = xl.r53[0][lane];
         __builtin_amdgcn_sched_barrier(0);
-        uint64_t t = 0;
-        for (; t + 2 <= nbits; t += 2) {
-            s_gen_clock<1>(x, r53, xl, lane);
-            s_gen_clock<0>(x, r53, xl, lane);
+        // clock pairs: the generated S loop of mickey128_loops.inc (the clocks of
+        // s_gen_clock<1>, s_gen_clock<0>), as many iterations as the R wave's
+        uint64_t npairs = nbits / 2;
+        while (npairs) {
+            const uint32_t iters = npairs > (1ull << 30) ? (1u << 30) : (uint32_t)npairs;
+            asm volatile("s_mov_b32 s24, %[it]\n1:\n\t" M128_S_LOOP_BODY
+                         "\n\ts_sub_u32 s24, s24, 1\n\ts_cmp_lg_u32 s24, 0\n\ts_cbranch_scc1 1b"
+                         : M128_S_LOOP_STATE(M128_LOOP_S, r53)
+                         : [it] "s"(iters), [xaddr] "v"(xaddr)
+                         : M128_S_LOOP_CLOBBERS, "s24", "scc", "memory");
+            npairs -= iters;
         }
-        if (t < nbits) s_gen_clock<1>(x, r53, xl, lane);
-        uint32_t v = g;
+        if (nbits & 1) s_gen_clock<1>(x, r53, xl, lane);
+        uint32_t v = g * 4u;
         asm volatile("" : "+v"(v));
 #pragma unroll
-        for (int j = 0; j < kN; j++) state[(size_t)(kN + j) * pitch + v] = x.s[j];
+        for (int j = 0; j < kN; j++) *(uint32_t *)((char *)state + (size_t)(kN + j) * pitch * 4u + v) = x.s[j];
     }
 }
 
