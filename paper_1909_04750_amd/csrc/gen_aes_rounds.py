@@ -300,7 +300,7 @@ def render() -> str:
     out.append("#define AES_ROUNDS_STATE(ST) \\\n    %s" % ", \\\n    ".join(state))
     out.append("#define AES_ROUNDS_CLOBBERS %s" % ", ".join(
         ['"v%d"' % r for r in clob] + ['"s%d"' % s for s in range(KEY_SGPR0, KEY_SGPR0 + 16)] +
-        ['"s%d"' % s for s in MASK_SGPRS]))
+        ['"s%d"' % s for s in MASK_SGPRS] + ['"scc"']))  # s_bfe_i32 writes SCC
     return "\n".join(out) + "\n"
 
 
