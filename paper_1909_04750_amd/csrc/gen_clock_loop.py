@@ -35,6 +35,7 @@ import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 OUT = os.path.join(HERE, "mickey_clock_loop.inc")
+OUT_MIX = os.path.join(HERE, "mickey_mix_loop.inc")
 
 TA, TB, TC = 0xF0, 0xCC, 0xAA
 N = 100
@@ -44,6 +45,7 @@ R0 = 8           # r_i in v[R0 + i]
 S0 = 112         # the S ring: v[S0 .. S0 + 99]
 SPARE_R = 108    # r_99 of odd clocks
 TEMPS = list(range(212, 256)) + list(range(4, 8)) + [109, 110, 111]  # c_R copies, c_S, g0, g1, z
+MIX_IN = [4, 5]  # the mixing body's input words (clock 0, clock 1 of the pair)
 
 
 def tables():
@@ -62,13 +64,16 @@ class Op:
         self.kind, self.text, self.dst, self.srcs = kind, text, dst, list(srcs)
 
 
-def build(tab):
-    """The CLOCKS-clock body as ops on physical registers, in program order."""
+def build(tab, mix=False):
+    """The CLOCKS-clock body as ops on physical registers, in program order.  With mix, the
+    initialisation clock instead (CLOCK_KG with mixing on, input word MIX_IN[t] of the
+    pair): fb_R = r_99 ^ in ^ s_50 and fb_S = s_99 ^ in in temporaries, the new s_0 (= fb_S)
+    moved into the register the ring gives it, and no keystream store."""
     ops = []
     rr = {i: R0 + i for i in range(N)}          # where r_i lives
     ring = [S0 + i for i in range(N)]           # where s_i lives: ring[i]
     zregs = [TEMPS[0], TEMPS[1]]                # keystream words, one per clock of the pair
-    free_temps = [t for t in TEMPS if t not in zregs]
+    free_temps = [t for t in TEMPS if t not in zregs and not (mix and t in MIX_IN)]
 
     def take(avoid_banks=()):
         for k, v in enumerate(free_temps):
@@ -91,25 +96,33 @@ def build(tab):
     spare_r = SPARE_R
     for t in range(CLOCKS):
         ascending = t % 2 == 0
-        # keystream word of the current state, and its store (plane address advanced by SALU)
-        z = zregs[t % 2]
-        v2("v_xor_b32", z, rr[0], ring[0])
-        ops.append(Op("store", "buffer_store_dword v%d, %%[voff], s[20:23], 0 offen" % z, None, (z,)))
-        ops.append(Op("salu", "s_add_u32 s20, s20, %[pitch]\n\ts_addc_u32 s21, s21, 0", None, ()))
+        if not mix:
+            # keystream word of the current state, and its store (plane address advanced by SALU)
+            z = zregs[t % 2]
+            v2("v_xor_b32", z, rr[0], ring[0])
+            ops.append(Op("store", "buffer_store_dword v%d, %%[voff], s[20:23], 0 offen" % z, None, (z,)))
+            ops.append(Op("salu", "s_add_u32 s20, s20, %[pitch]\n\ts_addc_u32 s21, s21, 0", None, ()))
         # control bits and feedback selections
         cra, crb = take(avoid_banks=(1, 2, 3)), take(avoid_banks=(0, 1, 3))
         v2("v_xor_b32", cra, ring[34], rr[67])
         v2("v_xor_b32", crb, ring[34], rr[67])
         cs = take()
         v2("v_xor_b32", cs, ring[67], rr[33])
+        old_s99, old_r99 = ring[99], rr[99]
+        if mix:
+            fbs = take()
+            v2("v_xor_b32", fbs, ring[99], MIX_IN[t])
+            fbr = take()
+            v3(fbr, rr[99], MIX_IN[t], ring[50], 0x96)
+        else:
+            fbs, fbr = ring[99], rr[99]
         g1 = take()
-        v2("v_and_b32", g1, ring[99], cs)
+        v2("v_and_b32", g1, fbs, cs)
         g0 = take()
-        v2("v_xor_b32", g0, ring[99], g1)
+        v2("v_xor_b32", g0, fbs, g1)
         free_temps.append(cs)
-        fbs = ring[99]
-        # R sweep, descending, in place; r_99 goes to the spare (old r_99 is the feedback)
-        fbr = rr[99]
+        # R sweep, descending, in place; r_99 goes to the spare (old r_99 is read by the
+        # feedback and by its own update)
         imm_r = (TA ^ (TB & TC)) & 0xFF
         for i in range(N - 1, -1, -1):
             if i == 0:
@@ -120,8 +133,10 @@ def build(tab):
             v3(dst, a, pick_c(cra, crb, a, b), b, imm_r)
             if i in tab["kRTaps"]:
                 v2("v_xor_b32", dst, dst, fbr)
-        rr[N - 1], spare_r = spare_r, fbr  # old r_99's register is free after the sweep
+        rr[N - 1], spare_r = spare_r, old_r99  # old r_99's register is free after the sweep
         free_temps += [cra, crb]
+        if mix:
+            free_temps.append(fbr)
 
         # S sweep
         def sel_of(i):
@@ -154,6 +169,11 @@ def build(tab):
             freed = [ring[0], ring[1]]
             ring = [ring[N - 1]] + ring[2:N - 1] + [t98, t99]
             free_temps += freed
+        if mix:
+            # the new s_0 is fb_S; the ring gives it the old s_99's register
+            assert ring[0] == old_s99
+            ops.append(Op("valu", "v_mov_b32 v%d, v%d" % (old_s99, fbs), old_s99, (fbs,)))
+            free_temps.append(fbs)
         free_temps += [g0, g1]
     # return every S word to its home register (a parallel move over the displaced ones)
     home = [S0 + i for i in range(N)]
@@ -250,9 +270,33 @@ def render() -> str:
     return "\n".join(out) + "\n"
 
 
+def render_mix() -> str:
+    tab = tables()
+    ops, rr, ring = build(tab, mix=True)
+    assert rr == {i: R0 + i for i in range(N)}, "R registers must return to their homes"
+    assert ring == [S0 + i for i in range(N)], "the S ring must return to its origin"
+    sched = schedule(ops)
+    nvalu = sum(o.kind == "valu" for o in sched)
+    body = "\n\t".join(o.text.replace("\n", "\n\t") for o in sched)
+    used = sorted({r for o in ops for r in list(o.srcs) + ([o.dst] if o.dst is not None else [])})
+    clob = [r for r in used if not (R0 <= r < R0 + N or S0 <= r < S0 + N) and r not in MIX_IN]
+    out = ["// Generated by gen_clock_loop.py from the tables of mickey_bitslice.h; do not edit.",
+           "// Initialisation (mixing) clocks: %d per body, %d VALU (%.1f per clock), %d bitop3 bank clashes."
+           % (CLOCKS, nvalu, nvalu / CLOCKS, clashes(sched)),
+           "#define MICKEY_MIX_CLOCKS %d" % CLOCKS,
+           "#define MICKEY_MIX_BODY \\\n    \"%s\\n\"" % body.replace("\n", "\\n\" \\\n    \"").replace("\t", "\\t"),
+           "#define MICKEY_MIX_INPUTS(IN0, IN1) \"{v%d}\"(IN0), \"{v%d}\"(IN1)" % (MIX_IN[0], MIX_IN[1]),
+           "#define MICKEY_MIX_CLOBBERS %s" % ", ".join('"v%d"' % r for r in clob)]
+    return "\n".join(out) + "\n"
+
+
 def main():
     text = render()
     with open(OUT, "w") as f:
+        f.write(text)
+    print(text.split("\n")[1])
+    text = render_mix()
+    with open(OUT_MIX, "w") as f:
         f.write(text)
     print(text.split("\n")[1])
 

@@ -65,3 +65,51 @@ def test_loop_body_equals_oracle_clocks():
             end_r = [(int(regs[v][lane]) >> bit) & 1 for v, k, i in homes if k == "R"]
             end_s = [(int(regs[v][lane]) >> bit) & 1 for v, k, i in homes if k == "S"]
             assert list(st.r) == end_r and list(st.s) == end_s, (lane, bit)
+
+
+MIX_INC = os.path.join(CSRC, "mickey_mix_loop.inc")
+
+
+def parse_mix():
+    import re
+    text = open(MIX_INC).read()
+    body = re.search(r"#define MICKEY_MIX_BODY \\\n(.*?)\n#define", text, re.S).group(1)
+    insts = [s.replace("\\t", "").replace("\\n", "").strip() for s in re.findall(r'"(.*?)"', body)]
+    insts = [i for i in insts if i]
+    ins = [int(v) for v in re.findall(r'"\{v(\d+)\}"\(IN\d\)', text)]
+    return insts, ins
+
+
+def test_committed_mix_loop_matches_generator():
+    assert generator().render_mix() == open(MIX_INC).read()
+
+
+def test_mix_loop_equals_oracle_initialisation_clocks():
+    """The initialisation body (CLOCK_KG with mixing on, one input word per clock) against
+    the oracle's clock, instance by instance (paper Sec. II-C-1: the key and IV bits enter
+    both registers, and s_50 R's feedback)."""
+    _, _, homes = parse_inc()
+    insts, ins = parse_mix()
+    assert len(ins) == 2
+    assert asm_emulator.written_before_read(insts, list(homes) + [(v, "I", 0) for v in ins])
+    rng = np.random.default_rng(2025)
+    lanes, iters = 2, 3
+    regs = {v: rng.integers(0, 2 ** 32, lanes, dtype=np.uint64).astype(np.uint32) for v in range(256)}
+    start = {(k, i): regs[v].copy() for v, k, i in homes}
+    inputs = []
+    for _ in range(iters):
+        words = [rng.integers(0, 2 ** 32, lanes, dtype=np.uint64).astype(np.uint32) for _ in range(2)]
+        inputs += words
+        for v, w in zip(ins, words):
+            regs[v] = w.copy()
+        assert emulate(insts, regs) == []  # no keystream stores
+    for lane in range(lanes):
+        for bit in (0, 9, 31):
+            st = oracle.State()
+            st.r[:] = [(int(start[("R", i)][lane]) >> bit) & 1 for i in range(100)]
+            st.s[:] = [(int(start[("S", i)][lane]) >> bit) & 1 for i in range(100)]
+            for w in inputs:
+                st.clock_kg(1, (int(w[lane]) >> bit) & 1)
+            end_r = [(int(regs[v][lane]) >> bit) & 1 for v, k, i in homes if k == "R"]
+            end_s = [(int(regs[v][lane]) >> bit) & 1 for v, k, i in homes if k == "S"]
+            assert list(st.r) == end_r and list(st.s) == end_s, (lane, bit)
