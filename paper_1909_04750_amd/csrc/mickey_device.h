@@ -179,6 +179,17 @@ __device__ __forceinline__ void store_global_f32(float *p, float v)
 {
     *(__attribute__((address_space(1))) float *)p = v;
 }
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+// Four consecutive words; p 16-byte aligned.
+__device__ __forceinline__ void store_global_x4(uint32_t *p, u32x4 v)
+{
+    *(__attribute__((address_space(1))) u32x4 *)p = v;
+}
+__device__ __forceinline__ void store_global_f32x4(float *p, f32x4 v)
+{
+    *(__attribute__((address_space(1))) f32x4 *)p = v;
+}
 
 // One keystream word (K 32-bit words) at the lane's offset in a wave-uniform plane: a
 // vector buffer store whose resource is built from the scalar plane address, so that the

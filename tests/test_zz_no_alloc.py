@@ -1,6 +1,6 @@
 """The allocation-free entry point, mickey_generate_rowmajor_noalloc, called through the C
 ABI, against the allocating one (mickey_generate_rowmajor) on the same inputs: two calls
-in a row, the second with a smaller input, bit for bit, and the states continuing alike."""
+in a row, each smaller than the one before, bit for bit, and the states continuing alike."""
 import ctypes
 
 import numpy as np
@@ -22,9 +22,12 @@ def inputs(seed, n):
 
 def test_noalloc_equals_allocating_entry_point_twice():
     lib = mickey.load_library()
+    # 1,088,000 instances: 864-clock chunks, so the transposes see tiles of 27 clock blocks
+    # and rows that start at word 0, 27, 54, 81 and 108 (aligned and unaligned stores);
     # 2^20 + 320 instances: the snapshot takes 25 MiB of the array, leaving 896-clock chunks;
-    # the second call is smaller in both instances and clocks (8192-clock chunks)
-    for n, nbits, seed in (((1 << 20) + 320, 4 * 1024 + 96, 1), (3000, 8192 + 64, 2)):
+    # each call's output (instances x clocks) is smaller than the one before (the last one
+    # has 8192-clock chunks)
+    for n, nbits, seed in ((1088000, 4096, 3), ((1 << 20) + 320, 4 * 1024 + 96, 1), (3000, 8192 + 64, 2)):
         k, v, b = inputs(seed, n)
         ref = mickey.Mickey(k, v, b)
         new = mickey.Mickey(k, v, b)
