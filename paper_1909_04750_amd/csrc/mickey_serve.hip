@@ -310,11 +310,19 @@ struct mickey_server {
     uint32_t *lane_left = nullptr, *lane_sid = nullptr;
     uint32_t *fresh = nullptr;  // per slice: lanes admitted since the last quantum
     uint32_t *sink = nullptr;   // per slice: target of stores by lanes without output
-    // staged quanta: keystream planes of one launch, and per lane what it wrote
-    uint32_t *zplanes = nullptr;
-    uint32_t **row_dst = nullptr;
-    uint32_t *row_cnt = nullptr;
+    // staged quanta: keystream planes of one launch, and per lane what it wrote; two
+    // buffers, so that a launch's rows are written (on tstream) while the next launch
+    // generates into the other buffer
+    uint32_t *zplanes[2] = {nullptr, nullptr};
+    uint32_t **row_dst[2] = {nullptr, nullptr};
+    uint32_t *row_cnt[2] = {nullptr, nullptr};
     uint32_t sub_blocks = 0;  // blocks per staged launch (0: staging not available)
+    uint64_t sub_seq = 0;     // staged launches so far: launch j uses buffer j & 1
+    hipStream_t tstream = nullptr;  // transposes and the completion counts
+    hipEvent_t ev_sub[2] = {nullptr, nullptr};    // launch into buffer k done
+    hipEvent_t ev_tdone[2] = {nullptr, nullptr};  // transpose of buffer k done
+    bool tdone_rec[2] = {false, false};
+    hipEvent_t ev_qend = nullptr;  // the quantum's last kernel on the server's stream
     int schedule = MICKEY_SCHED_AUTO, transpose = MICKEY_TRANSPOSE_AUTO;
     int simds = 1024;
     // latency streams: lane ids nlanes .. nlanes + kLatStreams - 1
@@ -379,9 +387,11 @@ void destroy(mickey_server *s)
 {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->tstream) (void)hipStreamSynchronize(s->tstream);
     for (void *p : {(void *)s->pool, (void *)s->planes, (void *)s->lane_out, (void *)s->lane_left,
                     (void *)s->lane_sid, (void *)s->fresh, (void *)s->sink, (void *)s->done_list,
-                    (void *)s->arena, (void *)s->zplanes, (void *)s->row_dst, (void *)s->row_cnt,
+                    (void *)s->arena, (void *)s->zplanes[0], (void *)s->row_dst[0], (void *)s->row_cnt[0],
+                    (void *)s->zplanes[1], (void *)s->row_dst[1], (void *)s->row_cnt[1],
                     (void *)s->lat_state, (void *)s->lat_out, (void *)s->lat_left, (void *)s->lat_sid,
                     (void *)s->lat_fresh})
         if (p) (void)hipFree(p);
@@ -389,8 +399,10 @@ void destroy(mickey_server *s)
         if (h) (void)hipHostFree(h);
     if (s->hcount) (void)hipHostFree(s->hcount);
     if (s->hlist) (void)hipHostFree(s->hlist);
-    for (hipEvent_t e : {s->ev[0], s->ev[1], s->ev_start[0], s->ev_start[1]})
+    for (hipEvent_t e : {s->ev[0], s->ev[1], s->ev_start[0], s->ev_start[1], s->ev_sub[0], s->ev_sub[1],
+                         s->ev_tdone[0], s->ev_tdone[1], s->ev_qend})
         if (e) (void)hipEventDestroy(e);
+    if (s->tstream) (void)hipStreamDestroy(s->tstream);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     if (s->side) {
         (void)hipStreamSynchronize(s->side);
@@ -708,9 +720,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     uint32_t *__restrict__ planes, uint32_t nslices, uint32_t nblocks, uint32_t **lane_out,
     uint32_t *__restrict__ lane_left, const uint32_t *__restrict__ lane_sid, uint8_t *__restrict__ pool,
     uint32_t *__restrict__ fresh, uint32_t *__restrict__ zplanes, uint32_t **row_dst, uint32_t *__restrict__ row_cnt,
-    uint32_t *__restrict__ done_list, uint32_t *__restrict__ done_count)
+    uint32_t *__restrict__ done_list, uint32_t *__restrict__ done_count, uint32_t raise_prio)
 {
     __shared__ Split4Lds xl;
+    // beside a transpose kernel, these waves take issue slots first (every wave of a
+    // workgroup waits at each clock's barrier for the slowest)
+    if (raise_prio) __builtin_amdgcn_s_setprio(3);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t g = blockIdx.x * 64u + lane;  // nslices is a multiple of 64
@@ -742,18 +757,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 // tiles of 16 slices x 1024 clocks as in the plain path's staged transpose.  Tiles whose
 // lanes have no word in the tile's clocks skip the plane reads.  The tile's 512 row
 // destinations and counts are read once, beside the plane reads, into LDS, so the stores
-// do not wait on a pointer load each.
-__global__ __launch_bounds__(256) void serve_transpose_kernel(const uint32_t *__restrict__ zplanes, uint32_t nslices,
-                                                              uint32_t nclocks, uint32_t *const *row_dst,
-                                                              const uint32_t *__restrict__ row_cnt)
+// do not wait on a pointer load each.  Called by every thread of the workgroup.
+__device__ __forceinline__ void serve_tile(uint32_t *lds, uint32_t **dsts, uint32_t *cnts,
+                                           const uint32_t *__restrict__ zplanes, uint32_t nslices, uint32_t nclocks,
+                                           uint32_t *const *row_dst, const uint32_t *__restrict__ row_cnt,
+                                           uint32_t s0, uint32_t t0)
 {
-    __shared__ uint32_t lds[kTpLdsWords];
-    __shared__ uint32_t *dsts[32 * kTpSlices];
-    __shared__ uint32_t cnts[32 * kTpSlices];
     const uint32_t tid = threadIdx.x;
-    const uint2 tb = tile_of_block();
-    const uint32_t s0 = tb.x * kTpSlices;
-    const uint32_t t0 = tb.y * kTpClocks;
     const uint32_t w0 = t0 / 32u;
     const uint32_t nb = min((uint32_t)kTpBlocks, (nclocks - t0) / 32u);
     const uint32_t c0 = row_cnt[32u * s0 + tid], c1 = row_cnt[32u * s0 + tid + 256u];
@@ -769,6 +779,42 @@ __global__ __launch_bounds__(256) void serve_transpose_kernel(const uint32_t *__
     if (w >= nb) return;
     for (uint32_t i = tid >> 5; i < 32u * kTpSlices; i += 8u) {
         if (w0 + w < cnts[i]) store_global(dsts[i] + w0 + w, tile_row_word(lds, i, w));
+    }
+}
+
+// One workgroup per tile.
+__global__ __launch_bounds__(256) void serve_transpose_kernel(const uint32_t *__restrict__ zplanes, uint32_t nslices,
+                                                              uint32_t nclocks, uint32_t *const *row_dst,
+                                                              const uint32_t *__restrict__ row_cnt)
+{
+    __shared__ uint32_t lds[kTpLdsWords];
+    __shared__ uint32_t *dsts[32 * kTpSlices];
+    __shared__ uint32_t cnts[32 * kTpSlices];
+    const uint2 tb = tile_of_block();
+    serve_tile(lds, dsts, cnts, zplanes, nslices, nclocks, row_dst, row_cnt, tb.x * kTpSlices, tb.y * kTpClocks);
+}
+
+// The same tiles (ntx slice tiles x nty clock tiles) taken by a fixed number of
+// workgroups (a multiple of 8) that loop over them, to run beside the next launch's
+// generate kernel with one workgroup on most CUs; workgroup g (on XCD g % 8) takes every
+// (grid / 8)-th tile of its XCD's contiguous share.
+__global__ __launch_bounds__(256) void serve_transpose_persistent_kernel(const uint32_t *__restrict__ zplanes,
+                                                                         uint32_t nslices, uint32_t nclocks,
+                                                                         uint32_t *const *row_dst,
+                                                                         const uint32_t *__restrict__ row_cnt,
+                                                                         uint32_t ntx, uint32_t nty)
+{
+    __shared__ uint32_t lds[kTpLdsWords];
+    __shared__ uint32_t *dsts[32 * kTpSlices];
+    __shared__ uint32_t cnts[32 * kTpSlices];
+    constexpr uint32_t kXcds = 8;
+    const uint32_t ntiles = ntx * nty;
+    const uint32_t x = blockIdx.x % kXcds, per = gridDim.x / kXcds;
+    const uint32_t hi = (uint32_t)((uint64_t)ntiles * (x + 1u) / kXcds);
+    for (uint32_t l = (uint32_t)((uint64_t)ntiles * x / kXcds) + blockIdx.x / kXcds; l < hi; l += per) {
+        serve_tile(lds, dsts, cnts, zplanes, nslices, nclocks, row_dst, row_cnt, (l % ntx) * kTpSlices,
+                   (l / ntx) * kTpClocks);
+        __syncthreads();  // the next tile reuses the LDS
     }
 }
 
@@ -1037,9 +1083,18 @@ mickey_server *mickey_server_create(const mickey_state *init, size_t nslices, ui
         (void)hipGetLastError();
     }
     bool okm = (s->sub_blocks == 0 ||
-                (hipMalloc(&s->zplanes, (size_t)s->sub_blocks * 32 * s->nslices * 4) == hipSuccess &&
-                 hipMalloc(&s->row_dst, s->nlanes * sizeof(uint32_t *)) == hipSuccess &&
-                 hipMalloc(&s->row_cnt, s->nlanes * 4) == hipSuccess)) &&
+                (hipMalloc(&s->zplanes[0], (size_t)s->sub_blocks * 32 * s->nslices * 4) == hipSuccess &&
+                 hipMalloc(&s->zplanes[1], (size_t)s->sub_blocks * 32 * s->nslices * 4) == hipSuccess &&
+                 hipMalloc(&s->row_dst[0], s->nlanes * sizeof(uint32_t *)) == hipSuccess &&
+                 hipMalloc(&s->row_dst[1], s->nlanes * sizeof(uint32_t *)) == hipSuccess &&
+                 hipMalloc(&s->row_cnt[0], s->nlanes * 4) == hipSuccess &&
+                 hipMalloc(&s->row_cnt[1], s->nlanes * 4) == hipSuccess)) &&
+               hipStreamCreateWithFlags(&s->tstream, hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&s->ev_sub[0], hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&s->ev_sub[1], hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&s->ev_tdone[0], hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&s->ev_tdone[1], hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&s->ev_qend, hipEventDisableTiming) == hipSuccess &&
                hipMalloc(&s->pool, 25 * s->nstates) == hipSuccess &&
                hipMalloc(&s->planes, 200 * s->nslices * 4) == hipSuccess &&
                hipMalloc(&s->lane_out, s->nlanes * sizeof(uint32_t *)) == hipSuccess &&
@@ -1155,27 +1210,49 @@ int launch_quantum(mickey_server *s, int b)
     const bool split4 = s->schedule == MICKEY_SCHED_SPLIT4 ||
                         (s->schedule == MICKEY_SCHED_AUTO && s->nslices / 64 < 2 * (size_t)s->simds);
     const bool split = s->schedule == MICKEY_SCHED_SPLIT;
+    // Launch j generates into buffer j & 1 on the server's stream; its rows are written on
+    // tstream, beside launch j + 1 (the next quantum's first launch, for a quantum's last).
+    // Beside the four-wave split the transposes run persistent on 7/8 of the CUs and the
+    // generator's waves at raised priority (as on the plain staged path).
+    const unsigned tp_wgs = (unsigned)(s->simds / 4 * 7 / 8) / 8 * 8;
     for (uint32_t b0 = 0; b0 < s->qblocks; b0 += s->sub_blocks) {
         const uint32_t nb = std::min(s->sub_blocks, s->qblocks - b0);
+        const int k = (int)(s->sub_seq & 1);
+        // the buffer's previous transpose has read it
+        if (s->tdone_rec[k] && hipStreamWaitEvent(s->stream, s->ev_tdone[k], 0) != hipSuccess)
+            return check_launch("staged buffer wait");
+        uint32_t *const zp = s->zplanes[k];
+        uint32_t **const rd = s->row_dst[k];
+        uint32_t *const rcnt = s->row_cnt[k];
         if (split4)
             hipLaunchKernelGGL(quantum_split4_kernel, dim3((unsigned)(s->nslices / 64)), dim3(256), 0, s->stream,
                                s->planes, (uint32_t)s->nslices, nb, s->lane_out, s->lane_left, s->lane_sid, s->pool,
-                               s->fresh, s->zplanes, s->row_dst, s->row_cnt, list, s->done_count + b);
+                               s->fresh, zp, rd, rcnt, list, s->done_count + b, (uint32_t)(tp_wgs > 0));
         else if (split)
             hipLaunchKernelGGL(quantum_split_kernel, dim3((unsigned)(s->nslices / 64)), dim3(128), 0, s->stream,
                                s->planes, (uint32_t)s->nslices, nb, s->lane_out, s->lane_left, s->lane_sid, s->pool,
-                               s->fresh, s->zplanes, s->row_dst, s->row_cnt, list, s->done_count + b);
+                               s->fresh, zp, rd, rcnt, list, s->done_count + b);
         else
             hipLaunchKernelGGL(quantum_planes_kernel, dim3((unsigned)(s->nslices / 64)), dim3(64), 0, s->stream,
                                s->planes, (uint32_t)s->nslices, nb, s->lane_out, s->lane_left, s->lane_sid, s->pool,
-                               s->fresh, s->zplanes, s->row_dst, s->row_cnt, list, s->done_count + b);
+                               s->fresh, zp, rd, rcnt, list, s->done_count + b);
         int rc = check_launch("quantum kernel");
         if (rc != MICKEY_OK) return rc;
+        s->sub_seq++;
+        if (hipEventRecord(s->ev_sub[k], s->stream) != hipSuccess ||
+            hipStreamWaitEvent(s->tstream, s->ev_sub[k], 0) != hipSuccess)
+            return check_launch("staged launch event");
         const dim3 grid((unsigned)(s->nslices / kTpSlices), (nb * 32 + kTpClocks - 1) / kTpClocks);
-        hipLaunchKernelGGL(serve_transpose_kernel, grid, dim3(256), 0, s->stream, s->zplanes, (uint32_t)s->nslices,
-                           nb * 32, s->row_dst, s->row_cnt);
+        if (split4 && tp_wgs > 0)
+            hipLaunchKernelGGL(serve_transpose_persistent_kernel, dim3(tp_wgs), dim3(256), 0, s->tstream, zp,
+                               (uint32_t)s->nslices, nb * 32, rd, rcnt, grid.x, grid.y);
+        else
+            hipLaunchKernelGGL(serve_transpose_kernel, grid, dim3(256), 0, s->tstream, zp, (uint32_t)s->nslices,
+                               nb * 32, rd, rcnt);
         rc = check_launch("serve_transpose_kernel");
         if (rc != MICKEY_OK) return rc;
+        if (hipEventRecord(s->ev_tdone[k], s->tstream) != hipSuccess) return check_launch("staged transpose event");
+        s->tdone_rec[k] = true;
     }
     return MICKEY_OK;
 }
@@ -1206,6 +1283,9 @@ int mickey_server_step(mickey_server *s)
     const bool any_bs = s->free_lanes.size() < s->nlanes, any_lat = s->lat_busy > 0;
     if (any_bs || any_lat) {
         const int b = (int)(s->next_q & 1);
+        // quantum next_q - 2 published this completion buffer's count on tstream
+        if (s->next_q >= 2 && hipStreamWaitEvent(s->stream, s->ev[b], 0) != hipSuccess)
+            return check_launch("completion buffer wait");
         if (hipEventRecord(s->ev_start[b], s->stream) != hipSuccess) return check_launch("quantum start");
         hipLaunchKernelGGL(reset_count_kernel, dim3(1), dim3(64), 0, s->stream, s->done_count + b);
         rc = check_launch("reset_count_kernel");
@@ -1229,10 +1309,16 @@ int mickey_server_step(mickey_server *s)
             if (rc != MICKEY_OK) return rc;
         }
         if (any_lat && hipStreamWaitEvent(s->stream, s->ev_join, 0) != hipSuccess) return check_launch("latency join");
-        hipLaunchKernelGGL(publish_count_kernel, dim3(1), dim3(64), 0, s->stream, s->done_count + b, s->hcount_dev + b);
+        // the completion count goes out on tstream, after the quantum's last transpose and
+        // its last kernel on the server's stream, so the next quantum's kernels need not
+        // wait for that transpose
+        if (hipEventRecord(s->ev_qend, s->stream) != hipSuccess ||
+            hipStreamWaitEvent(s->tstream, s->ev_qend, 0) != hipSuccess)
+            return check_launch("quantum end");
+        hipLaunchKernelGGL(publish_count_kernel, dim3(1), dim3(64), 0, s->tstream, s->done_count + b, s->hcount_dev + b);
         rc = check_launch("publish_count_kernel");
         if (rc != MICKEY_OK) return rc;
-        if (hipEventRecord(s->ev[b], s->stream) != hipSuccess) return check_launch("completion count");
+        if (hipEventRecord(s->ev[b], s->tstream) != hipSuccess) return check_launch("completion count");
         s->next_q++;
         s->steps++;
     }
