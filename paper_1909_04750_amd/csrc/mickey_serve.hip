@@ -1196,7 +1196,7 @@ int64_t mickey_server_submit(mickey_server *s, uint32_t state_id, uint64_t nbits
 // The quantum's kernels.  Staged (planes, then rows) unless staging is unavailable or
 // the fused path was asked for; within staged, the split schedule while the one-wave
 // kernel would have at most one wave per SIMD (the plain path's rule).
-int launch_quantum(mickey_server *s, int b)
+int launch_quantum(mickey_server *s, int b, bool lat_beside)
 {
     const bool staged = s->sub_blocks && s->transpose != MICKEY_TRANSPOSE_FUSED;
     uint32_t *const list = s->hlist_dev + (size_t)b * (s->nlanes + kLatStreams);
@@ -1213,8 +1213,10 @@ int launch_quantum(mickey_server *s, int b)
     // Launch j generates into buffer j & 1 on the server's stream; its rows are written on
     // tstream, beside launch j + 1 (the next quantum's first launch, for a quantum's last).
     // Beside the four-wave split the transposes run persistent on 7/8 of the CUs and the
-    // generator's waves at raised priority (as on the plain staged path).
-    const unsigned tp_wgs = (unsigned)(s->simds / 4 * 7 / 8) / 8 * 8;
+    // generator's waves at raised priority (as on the plain staged path), unless latency
+    // streams run beside the quantum too: their kernel then sets the pace, and would lose
+    // issue slots to both.
+    const unsigned tp_wgs = lat_beside ? 0u : (unsigned)(s->simds / 4 * 7 / 8) / 8 * 8;
     for (uint32_t b0 = 0; b0 < s->qblocks; b0 += s->sub_blocks) {
         const uint32_t nb = std::min(s->sub_blocks, s->qblocks - b0);
         const int k = (int)(s->sub_seq & 1);
@@ -1305,7 +1307,7 @@ int mickey_server_step(mickey_server *s)
             if (hipEventRecord(s->ev_join, s->side) != hipSuccess) return check_launch("latency join");
         }
         if (any_bs) {
-            rc = launch_quantum(s, b);
+            rc = launch_quantum(s, b, any_lat);
             if (rc != MICKEY_OK) return rc;
         }
         if (any_lat && hipStreamWaitEvent(s->stream, s->ev_join, 0) != hipSuccess) return check_launch("latency join");
