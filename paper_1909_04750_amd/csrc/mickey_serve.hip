@@ -775,10 +775,24 @@ __device__ __forceinline__ void serve_tile(uint32_t *lds, uint32_t **dsts, uint3
         dsts[tid] = d0;
         dsts[tid + 256u] = d1;
     });
-    const uint32_t w = tid & 31u;
-    if (w >= nb) return;
-    for (uint32_t i = tid >> 5; i < 32u * kTpSlices; i += 8u) {
-        if (w0 + w < cnts[i]) store_global(dsts[i] + w0 + w, tile_row_word(lds, i, w));
+    // four consecutive words of a row per thread (8 rows per store instruction) where the
+    // row's destination is 16-byte aligned and holds all four, else one word at a time
+    const uint32_t q = (tid & 7u) * 4u;
+    if (q >= nb) return;
+    for (uint32_t i = tid >> 3; i < 32u * kTpSlices; i += 32u) {
+        const uint32_t cnt = cnts[i];
+        if (w0 + q >= cnt) continue;
+        uint32_t *const d = dsts[i] + w0 + q;
+        if (q + 4u <= nb && w0 + q + 4u <= cnt && ((uintptr_t)d & 15u) == 0u) {
+            u32x4 v;
+            v.x = tile_row_word(lds, i, q);
+            v.y = tile_row_word(lds, i, q + 1u);
+            v.z = tile_row_word(lds, i, q + 2u);
+            v.w = tile_row_word(lds, i, q + 3u);
+            store_global_x4(d, v);
+        } else {
+            for (uint32_t k = 0; q + k < nb && w0 + q + k < cnt; k++) store_global(d + k, tile_row_word(lds, i, q + k));
+        }
     }
 }
 
