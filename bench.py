@@ -208,7 +208,8 @@ def bench_rowmajor(torch, mickey, synth, reps: int = 3):
         if name == "auto":
             res.update(leg)
             res["path"] = ("four-wave split schedule (%d waves) into 4096-clock bit-plane chunks (two 512 MiB "
-                           "buffers), each followed by the tiled transpose to u32 + f32 rows" % (4 * (n // 32 // 64)))
+                           "buffers); each chunk's tiled transpose to u32 + f32 rows runs on a second stream beside "
+                           "the next chunk's generation" % (4 * (n // 32 // 64)))
         else:
             res[name] = leg
     return res
