@@ -690,11 +690,7 @@ __device__ __forceinline__ void serve4_run(uint32_t *__restrict__ planes, size_t
     }
     char *plane = (char *)zplanes;  // wave-uniform (wave 0)
     uint32_t blk = 0;
-    // The loop runs while any lane of the wave is active, with all of them enabled: a lane
-    // whose words have all ended keeps clocking (as its ended instances do anyway), so the
-    // generated loop never runs under an exec mask that shrinks inside the loop.  blk is
-    // then the wave's block count; staged_advance caps each instance at its own words.
-    for (; blk < nblocks && __ballot(active != 0u) != 0ull; blk++) {
+    for (; blk < nblocks && active; blk++) {
         // the block's 32 clocks as 16 pairs (clock t writes exchange buffer (t + 1) & 1)
         s4_pairs<ROLE>(x, in, xl, lane, plane, voff, (uint32_t)pitch, 16u);
         plane += 32 * pitch;
