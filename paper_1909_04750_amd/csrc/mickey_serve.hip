@@ -1227,10 +1227,11 @@ int launch_quantum(mickey_server *s, int b, bool lat_beside)
     // Launch j generates into buffer j & 1 on the server's stream; its rows are written on
     // tstream, beside launch j + 1 (the next quantum's first launch, for a quantum's last).
     // Beside the four-wave split the transposes run persistent on 7/8 of the CUs and the
-    // generator's waves at raised priority (as on the plain staged path), unless latency
-    // streams run beside the quantum too: their kernel then sets the pace, and would lose
-    // issue slots to both.
+    // generator's waves at raised priority (as on the plain staged path).  When latency
+    // streams run beside the quantum, their kernel sets the pace and would lose issue slots
+    // to both: the transposes then follow each launch on the server's stream.
     const unsigned tp_wgs = lat_beside ? 0u : (unsigned)(s->simds / 4 * 7 / 8) / 8 * 8;
+    hipStream_t const ts = lat_beside ? s->stream : s->tstream;
     for (uint32_t b0 = 0; b0 < s->qblocks; b0 += s->sub_blocks) {
         const uint32_t nb = std::min(s->sub_blocks, s->qblocks - b0);
         const int k = (int)(s->sub_seq & 1);
@@ -1255,19 +1256,19 @@ int launch_quantum(mickey_server *s, int b, bool lat_beside)
         int rc = check_launch("quantum kernel");
         if (rc != MICKEY_OK) return rc;
         s->sub_seq++;
-        if (hipEventRecord(s->ev_sub[k], s->stream) != hipSuccess ||
-            hipStreamWaitEvent(s->tstream, s->ev_sub[k], 0) != hipSuccess)
+        if (ts != s->stream && (hipEventRecord(s->ev_sub[k], s->stream) != hipSuccess ||
+                                hipStreamWaitEvent(ts, s->ev_sub[k], 0) != hipSuccess))
             return check_launch("staged launch event");
         const dim3 grid((unsigned)(s->nslices / kTpSlices), (nb * 32 + kTpClocks - 1) / kTpClocks);
         if (split4 && tp_wgs > 0)
-            hipLaunchKernelGGL(serve_transpose_persistent_kernel, dim3(tp_wgs), dim3(256), 0, s->tstream, zp,
+            hipLaunchKernelGGL(serve_transpose_persistent_kernel, dim3(tp_wgs), dim3(256), 0, ts, zp,
                                (uint32_t)s->nslices, nb * 32, rd, rcnt, grid.x, grid.y);
         else
-            hipLaunchKernelGGL(serve_transpose_kernel, grid, dim3(256), 0, s->tstream, zp, (uint32_t)s->nslices,
-                               nb * 32, rd, rcnt);
+            hipLaunchKernelGGL(serve_transpose_kernel, grid, dim3(256), 0, ts, zp, (uint32_t)s->nslices, nb * 32,
+                               rd, rcnt);
         rc = check_launch("serve_transpose_kernel");
         if (rc != MICKEY_OK) return rc;
-        if (hipEventRecord(s->ev_tdone[k], s->tstream) != hipSuccess) return check_launch("staged transpose event");
+        if (hipEventRecord(s->ev_tdone[k], ts) != hipSuccess) return check_launch("staged transpose event");
         s->tdone_rec[k] = true;
     }
     return MICKEY_OK;
