@@ -182,7 +182,7 @@ int mickey_set_schedule(mickey_state *st, int schedule);
  *                            transposes its 32 x 32 block and stores one word per
  *                            instance (4-byte stores spread over 64 rows per instruction);
  *   MICKEY_TRANSPOSE_STAGED  the keystream goes to library-owned bit-plane buffers in
- *                            chunks of up to 8192 clocks (two buffers of at most 512 MiB,
+ *                            chunks of up to 8192 clocks (two buffers of at most 256 MiB,
  *                            allocated on first use, kept until mickey_free), and a tiled
  *                            transpose kernel writes 1024-clock row segments as whole
  *                            lines.  The transposes run on a library-owned second stream,
