@@ -207,7 +207,7 @@ def bench_rowmajor(torch, mickey, synth, reps: int = 3):
                "valu_frac": round(ops / (tg * 1e-3) / (VALU_PEAK_TOPS * 1e12), 4)}
         if name == "auto":
             res.update(leg)
-            res["path"] = ("four-wave split schedule (%d waves) into 4096-clock bit-plane chunks (two 512 MiB "
+            res["path"] = ("four-wave split schedule (%d waves) into 2048-clock bit-plane chunks (two 256 MiB "
                            "buffers); each chunk's tiled transpose to u32 + f32 rows runs on a second stream beside "
                            "the next chunk's generation" % (4 * (n // 32 // 64)))
         else:
