@@ -385,9 +385,11 @@ int mickey_server_set_chunk(mickey_server *s, uint64_t chunk_bytes);
 /* Kernels of the following quanta (the delivered bytes do not depend on them):
  *   transpose  MICKEY_TRANSPOSE_FUSED: one kernel stores every lane's word per 32 clocks
  *              into its request (one-wave schedule only); MICKEY_TRANSPOSE_STAGED: the
- *              quantum writes bit-planes to a server-owned buffer (at most 512 MiB, made
- *              at creation; a quantum whose planes exceed it runs as several launches)
- *              and a tiled transpose writes each request's words as whole lines;
+ *              quantum writes bit-planes to server-owned buffers (two of at most 512 MiB,
+ *              made at creation; a quantum whose planes exceed one runs as several
+ *              launches, alternating between them) and a tiled transpose writes each
+ *              request's words as whole lines, beside the next launch when no latency
+ *              stream runs;
  *              MICKEY_TRANSPOSE_AUTO: STAGED when the buffer exists (it does unless one
  *              32-clock launch of planes exceeds 512 MiB).
  *   schedule   for staged quanta, MICKEY_SCHED_ONE_WAVE / _SPLIT / _SPLIT4 / _AUTO as
