@@ -296,7 +296,7 @@ int launch_bitsliced(mickey_batch *b, const Variant &v)
     int rc = check_launch("reset_words_kernel");
     if (rc != MICKEY_OK) return rc;
     const uint32_t nslots = (uint32_t)(b->groups_pad * 32);
-    const dim3 sgrid(nslots / 256 + (nslots % 256 ? 1 : 0));
+    const dim3 sgrid((unsigned)((b->groups_pad + kStageSlices - 1) / kStageSlices));
     if (b->iv_bits)
         hipLaunchKernelGGL((stage_kernel<true, true>), sgrid, dim3(256), 0, b->stream, b->keys, b->ivs, b->iv_bits,
                            b->order, nslots, (uint32_t)b->groups_pad, b->in_planes, b->mask_planes, b->status);

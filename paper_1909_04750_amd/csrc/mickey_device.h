@@ -26,11 +26,15 @@ using bitops::transpose_half;
 // request order[i] when ORDER) with IV length L idles for d = 80 - L clocks and then
 // takes its L IV bits (MSB first), so the key always enters at clock 80 in every lane:
 // its input string is the 160-bit number (ivL << 80) | key read MSB first (ivL = the
-// L-bit IV), and its "started" string is d zeros then ones.  A block of 256 slots
-// (8 slices) writes these strings as 32-bit chunks to LDS; then one wave turns each
-// (slice, chunk) into 32 bit-planes with an in-register 32x32 transpose.
+// L-bit IV), and its "started" string is d zeros then ones.  A block of 256 threads
+// takes kStageSlices slices (32 slots each): it writes these strings as 32-bit chunks to
+// LDS, then turns each (chunk, slice) into 32 bit-planes with an in-register 32x32
+// transpose; a wave takes one chunk of 64 consecutive slices, so every plane store
+// writes 256 contiguous bytes.
 //   nslots: real slots (others are padding with an all-zero key and 80-bit IV)
-//   nslices: plane pitch in words (slots are 32*nslices)
+//   nslices: plane pitch in words (slots are 32*nslices); the grid is
+//            ceil(nslices / kStageSlices) blocks
+constexpr int kStageSlices = 64;
 template <bool MASKED, bool ORDER>
 __global__ __launch_bounds__(256) void stage_kernel(const uint8_t *__restrict__ keys,
                                                     const uint8_t *__restrict__ ivs,
@@ -41,65 +45,70 @@ __global__ __launch_bounds__(256) void stage_kernel(const uint8_t *__restrict__ 
                                                     uint32_t *__restrict__ status)
 {
     constexpr int kChunks = kInputPlanes / 32, kMaskChunks = kMaskPlanes / 32;
-    __shared__ uint32_t chunk[kChunks + kMaskChunks][256];
+    constexpr int kRows = kChunks + (MASKED ? kMaskChunks : 0);
+    constexpr uint32_t kStride = 33;  // words per slice in a chunk row: the pad puts a wave's 64
+                                      // column reads (one per slice) in different banks
+    __shared__ uint32_t chunk[kRows][kStageSlices * kStride];
     const uint32_t tid = threadIdx.x;
-    const uint32_t i = blockIdx.x * 256u + tid;
-    uint32_t req = i < nslots ? i : kNoRequest;
-    if (ORDER && req != kNoRequest) req = order[i];
-    uint64_t kh = 0, ih = 0;
-    uint32_t kl = 0, il = 0, L = 80;
-    if (req != kNoRequest) {
-        const uint8_t *k = keys + 10ull * req;
-        const uint8_t *v = ivs + 10ull * req;
+    for (uint32_t j = tid; j < 32u * kStageSlices; j += 256u) {
+        const uint32_t i = blockIdx.x * (32u * kStageSlices) + j;
+        uint32_t req = i < nslots ? i : kNoRequest;
+        if (ORDER && req != kNoRequest) req = order[i];
+        uint64_t kh = 0, ih = 0;
+        uint32_t kl = 0, il = 0, L = 80;
+        if (req != kNoRequest) {
+            const uint8_t *k = keys + 10ull * req;
+            const uint8_t *v = ivs + 10ull * req;
 #pragma unroll
-        for (int b = 0; b < 8; b++) {
-            kh = (kh << 8) | k[b];
-            ih = (ih << 8) | v[b];
+            for (int b = 0; b < 8; b++) {
+                kh = (kh << 8) | k[b];
+                ih = (ih << 8) | v[b];
+            }
+            kl = ((uint32_t)k[8] << 8) | k[9];
+            il = ((uint32_t)v[8] << 8) | v[9];
+            if (MASKED) {
+                L = iv_bits[req];
+                if (L > 80u) {
+                    atomicOr(status, 1u);
+                    L = 80u;
+                }
+            }
         }
-        kl = ((uint32_t)k[8] << 8) | k[9];
-        il = ((uint32_t)v[8] << 8) | v[9];
-        if (MASKED) {
-            L = iv_bits[req];
-            if (L > 80u) {
-                atomicOr(status, 1u);
-                L = 80u;
+        typedef unsigned __int128 u128;
+        const u128 key80 = ((u128)kh << 16) | kl;
+        const u128 iv80 = ((u128)ih << 16) | il;
+        const u128 ivL = L ? (iv80 >> (80u - L)) : (u128)0;
+        const u128 lo = key80 | (ivL << 80);  // bits 0..127 of the input string
+        const uint32_t at = (j >> 5) * kStride + (j & 31u);
+        chunk[0][at] = (uint32_t)(ivL >> 48);  // bits 159..128: clocks 0..31, MSB first
+        chunk[1][at] = (uint32_t)(lo >> 96);
+        chunk[2][at] = (uint32_t)(lo >> 64);
+        chunk[3][at] = (uint32_t)(lo >> 32);
+        chunk[4][at] = (uint32_t)lo;
+        if constexpr (MASKED) {
+            const uint32_t d = 80u - L;  // clocks before this lane starts
+#pragma unroll
+            for (int c = 0; c < kMaskChunks; c++) {
+                const uint32_t first = 32u * c;  // started bit of clock first+b is (first+b >= d)
+                chunk[kChunks + c][at] =
+                    d <= first ? 0xFFFFFFFFu : (d >= first + 32u ? 0u : (0xFFFFFFFFu >> (d - first)));
             }
         }
     }
-    typedef unsigned __int128 u128;
-    const u128 key80 = ((u128)kh << 16) | kl;
-    const u128 iv80 = ((u128)ih << 16) | il;
-    const u128 ivL = L ? (iv80 >> (80u - L)) : (u128)0;
-    const u128 lo = key80 | (ivL << 80);    // bits 0..127 of the input string
-    chunk[0][tid] = (uint32_t)(ivL >> 48);  // bits 159..128: clocks 0..31, MSB first
-    chunk[1][tid] = (uint32_t)(lo >> 96);
-    chunk[2][tid] = (uint32_t)(lo >> 64);
-    chunk[3][tid] = (uint32_t)(lo >> 32);
-    chunk[4][tid] = (uint32_t)lo;
-    if (MASKED) {
-        const uint32_t d = 80u - L;  // clocks before this lane starts
-#pragma unroll
-        for (int c = 0; c < kMaskChunks; c++) {
-            const uint32_t first = 32u * c;  // started bit of clock first+b is (first+b >= d)
-            chunk[kChunks + c][tid] =
-                d <= first ? 0xFFFFFFFFu : (d >= first + 32u ? 0u : (0xFFFFFFFFu >> (d - first)));
-        }
-    }
     __syncthreads();
-    constexpr int kTasks = 8 * (kChunks + (MASKED ? kMaskChunks : 0));
-    static_assert(kTasks <= 64, "one wave does the transposes");
-    if (tid >= (uint32_t)kTasks) return;
-    const uint32_t sl = tid & 7u, c = tid >> 3;
-    const uint32_t slice = blockIdx.x * 8u + sl;
-    if (slice >= nslices) return;
-    uint32_t a[32];
+    for (uint32_t task = tid; task < (uint32_t)(kRows * kStageSlices); task += 256u) {
+        const uint32_t sl = task % kStageSlices, c = task / kStageSlices;
+        const uint32_t slice = blockIdx.x * kStageSlices + sl;
+        if (slice >= nslices) continue;
+        uint32_t a[32];
 #pragma unroll
-    for (int l = 0; l < 32; l++) a[l] = chunk[c][32u * sl + l];
-    transpose32(a);  // a[r] bit l = bit r of slot l's chunk word = clock 32c + 31 - r
-    uint32_t *dst = c < (uint32_t)kChunks ? in_planes + (size_t)(32u * c) * nslices
-                                          : mask_planes + (size_t)(32u * (c - kChunks)) * nslices;
+        for (int l = 0; l < 32; l++) a[l] = chunk[c][sl * kStride + l];
+        transpose32(a);  // a[r] bit l = bit r of slot l's chunk word = clock 32c + 31 - r
+        uint32_t *dst = c < (uint32_t)kChunks ? in_planes + (size_t)(32u * c) * nslices
+                                              : mask_planes + (size_t)(32u * (c - kChunks)) * nslices;
 #pragma unroll
-    for (int r = 0; r < 32; r++) dst[(size_t)(31 - r) * nslices + slice] = a[r];
+        for (int r = 0; r < 32; r++) dst[(size_t)(31 - r) * nslices + slice] = a[r];
+    }
 }
 
 __device__ __forceinline__ uint32_t ld_plane(const uint32_t *base, size_t pitch, uint32_t t, uint32_t voff)
